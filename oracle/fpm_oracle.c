@@ -457,7 +457,11 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
   double *S = S_out, *P = P_out;
 
   /* Initial guess (reading: the paper does not state one): S = 0 except the
-   * first LED's window, which takes shift(FFT_n(sqrt I_j0)); P = P_init. */
+   * centred n x n window, which takes shift(FFT_n(sqrt I_j0)) of the first
+   * LED's image; P = P_init.  The intensity keeps no trace of the
+   * illumination tilt (Sec. 2.2: the tilt only shifts the spectrum, and the
+   * modulus drops the resulting phase ramp), so sqrt(I_j0) estimates |o| and
+   * its spectrum is centred on the object's zero frequency. */
   if (S_in) {
     memcpy(S, S_in, sizeof(double) * 2 * NN);
   } else {
@@ -470,8 +474,7 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
     }
     orc_fft2(w.phi, n, n, -1);
     shift2(w.phi, w.tmp, n, n);
-    int wy, wx;
-    window_origin(g, off, j0, &wy, &wx);
+    const int wy = N / 2 - n / 2, wx = N / 2 - n / 2;
     for (int u = 0; u < n; ++u)
       for (int v = 0; v < n; ++v) {
         double *xo = S + 2 * ((size_t)(wy + u) * N + (wx + v));
