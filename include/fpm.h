@@ -1,0 +1,227 @@
+/*
+ * fpm.h -- C ABI of the MI355X (gfx950) Fourier ptychographic reconstruction
+ * library (libfpm.so).
+ *
+ * The method is the one of Zhou et al., "Parallel Fourier Ptychography
+ * reconstruction": alternating projections between the spatial modulus
+ * constraint and the frequency support constraint (Sec. 1, Sec. 2.1),
+ * run independently per overlapping sub-region with its own illumination
+ * angles and defocus (Sec. 2.2, Sec. 3.1), and across groups of LEDs whose
+ * spectrum regions do not overlap (Sec. 3.2), on FFT/IFFT kernels written
+ * for the GPU (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ *  - Complex data are interleaved float pairs (complex64), row-major.
+ *  - Spectra are centred: index u is frequency (u - size/2) / (n * pixel_um).
+ *  - LED index j = r * led_cols + c is the board (grid) index, row-major;
+ *    it is not the processing order.
+ *  - Multi-tile arrays are the per-tile arrays concatenated in plan order;
+ *    tile t of a plan starts at the element offset the plan reports.
+ *  - Ownership: the caller owns every buffer it passes; buffers must stay
+ *    valid until the call returns (fpm_submit: until fpm_poll has returned
+ *    a status other than FPM_PENDING).  The library owns plans, servers and
+ *    all device-resident state it allocates.
+ *  - Device pointers and streams: FPM_MEM_DEVICE pointers are HIP device
+ *    addresses on the current device; `hip_stream` is a hipStream_t cast to
+ *    void* (NULL = the default stream).
+ *  - Errors: every call returns an fpm_status; nothing is thrown across the
+ *    ABI.  fpm_last_error() gives a thread-local message for the last
+ *    non-OK status.  On error no output buffer is written.
+ */
+#ifndef FPM_H
+#define FPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FPM_OK = 0,
+  FPM_PENDING = 1,        /* fpm_poll: the request has not finished          */
+  FPM_E_ARG = -1,         /* invalid argument (NULL, size, non-finite data)   */
+  FPM_E_GEOMETRY = -2,    /* a crop window leaves the high-resolution grid    */
+  FPM_E_NOMEM = -3,       /* device or host allocation failed                 */
+  FPM_E_DEVICE = -4,      /* a HIP call failed                                */
+  FPM_E_DIVERGED = -5,    /* a residual became non-finite                     */
+  FPM_E_CANCELLED = -6,   /* the request was cancelled                        */
+  FPM_E_UNSUPPORTED = -7  /* tile size or precision this build does not run   */
+} fpm_status;
+
+typedef enum {
+  FPM_PREC_FP32_FFT = 0,     /* FP32 FFTs in LDS and registers (default)    */
+  FPM_PREC_MFMA_BF16X3 = 1,  /* dense DFT on MFMA, three-term split bf16    */
+  FPM_PREC_MFMA_FP16 = 2     /* dense DFT on MFMA, scaled fp16              */
+} fpm_precision;
+
+typedef enum {
+  FPM_SCHED_SEQUENTIAL = 0,  /* one LED at a time, ascending illumination NA */
+  FPM_SCHED_LED_GROUPS = 1,  /* Sec. 3.2: members of a non-overlapping LED
+                                group run concurrently from the group-start
+                                state; the pupil takes their mean increment  */
+  FPM_SCHED_GROUP_ORDER = 2  /* one LED at a time, in the grouped order      */
+} fpm_schedule;
+
+typedef enum { FPM_MEM_HOST = 0, FPM_MEM_DEVICE = 1 } fpm_mem;
+
+/* One tile = one independent reconstruction (Sec. 3.1).  The fields are the
+ * paper's problem statement: LED board geometry and height (Sec. 2.2,
+ * Sec. 4), wavelength and objective NA (Sec. 2.1), effective pixel size
+ * (Sec. 4), the sub-region's position and defocus (Sec. 2.2), iterations
+ * (Sec. 2.1, Sec. 4.1), plus the upsampling factor of the synthesised grid.
+ *
+ * Geometry (all FP64, evaluated left to right as written):
+ *   LED (r, c):  x = (c - (led_cols-1)/2) * led_pitch_um + led_origin_x_um
+ *                y = (r - (led_rows-1)/2) * led_pitch_um + led_origin_y_um
+ *   rho  = sqrt((x - tile_x)^2 + (y - tile_y)^2 + led_height^2)
+ *   dcol = floor((x - tile_x)/rho * n * pixel_um / wavelength_um + 0.5)
+ *   drow = floor((y - tile_y)/rho * n * pixel_um / wavelength_um + 0.5)
+ *   support radius r = na_obj * n * pixel_um / wavelength_um (bins);
+ *   D0 = {(u,v) : (u - n/2)^2 + (v - n/2)^2 <= r^2}.
+ *   LED j's window in the N x N spectrum (N = n * upsample): rows
+ *   [N/2 + drow - n/2, +n), cols [N/2 + dcol - n/2, +n); |drow|, |dcol| must
+ *   not exceed (N - n)/2, else FPM_E_GEOMETRY. */
+typedef struct {
+  int32_t n;              /* LR tile side in pixels: 64, 96 or 128 (even)     */
+  int32_t upsample;       /* HR side N = n * upsample                         */
+  int32_t led_rows, led_cols;
+  double led_pitch_um, led_height_um;
+  double led_origin_x_um, led_origin_y_um;
+  double wavelength_um, na_obj, pixel_um;  /* pixel_um: sample-plane LR pixel */
+  double tile_x_um, tile_y_um;             /* tile centre w.r.t. optical axis */
+  double defocus_um;                       /* tile defocus z                  */
+  int32_t iterations;
+  int32_t pupil_update;                    /* 0 or 1                          */
+  int32_t precision;                       /* fpm_precision                   */
+  int32_t schedule;                        /* fpm_schedule                    */
+} fpm_tile_desc;
+
+/* Per-tile facts a plan derives (fpm_plan_tile_info). */
+typedef struct {
+  int32_t n, N, L;             /* LR side, HR side, LED count               */
+  int32_t support_count;       /* |D0|                                       */
+  int32_t ngroups;             /* non-overlapping LED groups (Sec. 3.2)      */
+  int32_t max_group;           /* largest group                              */
+  int32_t steps;               /* dependent update steps per iteration       */
+  int32_t iterations;
+  double min_tie_distance;     /* min |frac(offset) - 0.5| over LEDs/axes    */
+  int64_t intensity_offset;    /* element offset of this tile's [L][n][n]    */
+  int64_t object_offset;       /* complex offset of this tile's [N][N]       */
+  int64_t pupil_offset;        /* complex offset of this tile's [n][n]       */
+  int64_t residual_offset;     /* offset of this tile's [iterations] doubles */
+} fpm_tile_info;
+
+typedef struct fpm_plan_s fpm_plan_t;
+typedef struct fpm_server_s fpm_server_t;
+
+/* Build a plan for `ntiles` independent tiles (Sec. 3.1).  Host-only FP64
+ * geometry: integer spectrum offsets per LED (Sec. 2.2), the processing
+ * order (ascending illumination NA; Sec. 3.2 Fig. 6a), the non-overlapping
+ * LED groups (greedy first fit over that order; Sec. 3.2), the support D0
+ * and the initial pupil D0 * exp(i phi_z) with the tile's defocus phase.
+ * Device memory is allocated on first use, on the current device.
+ * Errors: FPM_E_ARG (NULL, ntiles < 1, unsupported field values),
+ * FPM_E_GEOMETRY (a window outside the HR grid), FPM_E_UNSUPPORTED. */
+fpm_status fpm_plan(const fpm_tile_desc *tiles, int32_t ntiles, fpm_plan_t **out);
+void fpm_plan_destroy(fpm_plan_t *plan);
+
+fpm_status fpm_plan_tile_info(const fpm_plan_t *plan, int32_t tile, fpm_tile_info *info);
+
+/* Host copies of tile `tile`'s integer tables, each optional (NULL skips):
+ * offsets [L][2] (drow, dcol) per grid LED; order [L] (grid indices in
+ * ascending illumination NA); group_of [L] (group of each grid LED);
+ * sweep [L] (groups concatenated, members in order). */
+fpm_status fpm_plan_tables(const fpm_plan_t *plan, int32_t tile, int32_t *offsets,
+                           int32_t *order, int32_t *group_of, int32_t *sweep);
+
+/* Device bytes the plan holds once fpm_reconstruct has run (state, scratch,
+ * work lists; excluding caller buffers). */
+fpm_status fpm_plan_device_bytes(const fpm_plan_t *plan, size_t *bytes);
+
+/* Forward model (Sec. 2.1, Fig. 1): for every tile and grid LED j,
+ * I_j = |IFFT_n(shift(P * W_j(S)))|^2 with S = shift(FFT_N(object)) / up^2.
+ *   object    complex64 [tile][N][N], spatial domain.
+ *   pupil     complex64 [tile][n][n] centred, or NULL for the plan's initial
+ *             pupil; only its values on D0 are used.
+ *   intensity float [tile][L][n][n] output.
+ * `where` applies to all three buffers.  Device mode enqueues on
+ * `hip_stream` and returns; host mode copies and synchronises. */
+fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
+                       float *intensity, fpm_mem where, void *hip_stream);
+
+/* Reconstruction (Sec. 2.1 Fig. 2 with embedded pupil recovery; Sec. 3.1
+ * tiles; Sec. 3.2 LED groups).  Per tile, from the initial guess
+ * S = 0 except the centred n x n window = shift(FFT_n(sqrt I_j0)) (j0 the
+ * first LED of the sweep; an intensity carries no illumination tilt, so its
+ * spectrum sits at zero frequency), P = P_init, for each iteration and each
+ * LED j of the schedule:
+ *   X = W_j(S), Phi = P X, psi = IFFT_n(shift Phi),
+ *   psi' = sqrt(I_j) psi / |psi|, Phi' = shift FFT_n(psi'), D = Phi' - Phi,
+ *   W_j(S) <- X + conj(P) D / max|P|^2          on D0,
+ *   P      <- P + conj(X) D / max|S|^2          on D0 (pupil_update),
+ * where max|S|^2 is taken over the whole spectrum at the start of the
+ * iteration; LED groups read the group-start state and average their pupil
+ * increments.  After each iteration: residual = sum (|psi| - sqrt I)^2 /
+ * sum I (FP64), and, with pupil_update, the pupil energy is normalised to
+ * |D0| (P <- sP, S <- S/s; the product P*S is unchanged).
+ *   intensity     float [tile][L][n][n] (grid LED order), finite, >= 0.
+ *   object_out    complex64 [tile][N][N]: up^2 * IFFT_N(shift S); may be NULL.
+ *   pupil_out     complex64 [tile][n][n]; may be NULL.
+ *   residual_out  double [tile][iterations]; may be NULL.
+ * `where` applies to all four buffers.  FPM_MEM_DEVICE: enqueued on
+ * `hip_stream`, returns without waiting (intensities are not validated).
+ * FPM_MEM_HOST: the intensities are validated (FPM_E_ARG on NaN, Inf or a
+ * negative value), copied, and the call synchronises; FPM_E_DIVERGED if a
+ * residual is not finite. */
+fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem where,
+                           void *object_out, void *pupil_out, double *residual_out,
+                           void *hip_stream);
+
+/* ------------------------------------------------------------ serving */
+
+typedef struct {
+  double submit_s;      /* seconds since server start                     */
+  double admit_s;       /* admitted (device memory granted)               */
+  double finish_s;      /* outputs ready                                  */
+  int64_t updates;      /* LED-tile updates the request ran               */
+  int32_t status;       /* final fpm_status of the request                */
+} fpm_request_stats;
+
+/* A request loop on its own host thread: requests are admitted while their
+ * device footprint fits `hbm_budget_bytes` and fewer than `max_slots` run;
+ * every admitted request keeps its spectrum and pupil resident; each
+ * scheduler tick launches the next dependent step of every admitted request
+ * together (continuous batching).  Errors: FPM_E_ARG, FPM_E_DEVICE. */
+fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t **out);
+void fpm_server_destroy(fpm_server_t *server);
+
+/* Enqueue one tile reconstruction.  `intensity` is float [L][n][n] in host
+ * or device memory per `where`; it must stay valid until fpm_poll returns
+ * non-PENDING.  Returns at once with a request id. */
+fpm_status fpm_submit(fpm_server_t *server, const fpm_tile_desc *tile, const float *intensity,
+                      fpm_mem where, uint64_t *id);
+
+/* FPM_PENDING while the request runs; else its final status, having copied
+ * the outputs (host memory; each may be NULL) and released the request. */
+fpm_status fpm_poll(fpm_server_t *server, uint64_t id, void *object_out, void *pupil_out,
+                    double *residual_out, fpm_request_stats *stats);
+
+/* Wait until request `id` is no longer pending (or `timeout_s` passes), then
+ * behave as fpm_poll. */
+fpm_status fpm_wait(fpm_server_t *server, uint64_t id, double timeout_s, void *object_out,
+                    void *pupil_out, double *residual_out, fpm_request_stats *stats);
+
+/* Cancel a request: frees its slot; other requests are unaffected. */
+fpm_status fpm_cancel(fpm_server_t *server, uint64_t id);
+
+/* Thread-local text of the last non-OK status on this thread. */
+const char *fpm_last_error(void);
+/* Library version string. */
+const char *fpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPM_H */

@@ -1,0 +1,270 @@
+// C ABI entry points for plans (include/fpm.h).  No exception crosses the
+// boundary; every failure becomes an fpm_status plus a thread-local message.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fpm_internal.h"
+#include "runtime.h"
+
+struct fpm_plan_s {
+  std::vector<fpm::TilePlan> tiles;
+  int device = -1;
+  fpm::Executor exec;
+  std::mutex mu;
+};
+
+namespace fpm {
+namespace {
+
+bool use_graphs() {
+  const char* v = std::getenv("FPM_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+// Make the plan's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  DeviceGuard(fpm_plan_t* p) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (p->device < 0) p->device = prev;
+    if (p->device != prev && hipSetDevice(p->device) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+fpm_status ensure_setup(fpm_plan_t* p) {
+  if (p->exec.ready) return FPM_OK;
+  return p->exec.setup(p->tiles);
+}
+
+}  // namespace
+}  // namespace fpm
+
+using namespace fpm;
+
+extern "C" {
+
+const char* fpm_last_error(void) { return g_last_error.c_str(); }
+
+const char* fpm_version(void) { return "fpm-mi355x 0.1 (gfx950)"; }
+
+fpm_status fpm_plan(const fpm_tile_desc* tiles, int32_t ntiles, fpm_plan_t** out) {
+  if (!tiles || !out || ntiles < 1 || ntiles > (1 << 20))
+    return fail(FPM_E_ARG, "fpm_plan: NULL argument or ntiles out of range");
+  *out = nullptr;
+  fpm_plan_t* p = new (std::nothrow) fpm_plan_t();
+  if (!p) return fail(FPM_E_NOMEM, "fpm_plan: host allocation failed");
+  p->tiles.resize(ntiles);
+  int64_t io = 0, oo = 0, po = 0, ro = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    std::string err;
+    const fpm_status s = build_tile_plan(tiles[t], p->tiles[t], err);
+    if (s != FPM_OK) {
+      delete p;
+      return fail(s, "tile " + std::to_string(t) + ": " + err);
+    }
+    TilePlan& tp = p->tiles[t];
+    tp.i_off = io;
+    tp.o_off = oo;
+    tp.p_off = po;
+    tp.r_off = ro;
+    io += (int64_t)tp.L * tp.n * tp.n;
+    oo += (int64_t)tp.N * tp.N;
+    po += (int64_t)tp.n * tp.n;
+    ro += tp.d.iterations;
+  }
+  *out = p;
+  return FPM_OK;
+}
+
+void fpm_plan_destroy(fpm_plan_t* plan) {
+  if (!plan) return;
+  if (plan->device >= 0) {  // device state exists only once a call has run
+    DeviceGuard g(plan);
+    (void)hipDeviceSynchronize();
+    plan->exec.~Executor();
+    new (&plan->exec) Executor();
+  }
+  delete plan;
+}
+
+fpm_status fpm_plan_tile_info(const fpm_plan_t* plan, int32_t tile, fpm_tile_info* info) {
+  if (!plan || !info || tile < 0 || tile >= (int)plan->tiles.size())
+    return fail(FPM_E_ARG, "fpm_plan_tile_info: bad argument");
+  const TilePlan& tp = plan->tiles[tile];
+  info->n = tp.n;
+  info->N = tp.N;
+  info->L = tp.L;
+  info->support_count = tp.nd0;
+  info->ngroups = tp.ngroups;
+  info->max_group = tp.max_group;
+  info->steps = tp.nsteps;
+  info->iterations = tp.d.iterations;
+  info->min_tie_distance = tp.min_tie;
+  info->intensity_offset = tp.i_off;
+  info->object_offset = tp.o_off;
+  info->pupil_offset = tp.p_off;
+  info->residual_offset = tp.r_off;
+  return FPM_OK;
+}
+
+fpm_status fpm_plan_tables(const fpm_plan_t* plan, int32_t tile, int32_t* offsets, int32_t* order,
+                           int32_t* group_of, int32_t* sweep) {
+  if (!plan || tile < 0 || tile >= (int)plan->tiles.size())
+    return fail(FPM_E_ARG, "fpm_plan_tables: bad argument");
+  const TilePlan& tp = plan->tiles[tile];
+  if (offsets) std::memcpy(offsets, tp.off.data(), sizeof(int32_t) * 2 * tp.L);
+  if (order) std::memcpy(order, tp.order.data(), sizeof(int32_t) * tp.L);
+  if (group_of) std::memcpy(group_of, tp.group_of.data(), sizeof(int32_t) * tp.L);
+  if (sweep) std::memcpy(sweep, tp.sweep.data(), sizeof(int32_t) * tp.L);
+  return FPM_OK;
+}
+
+fpm_status fpm_plan_device_bytes(const fpm_plan_t* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(FPM_E_ARG, "fpm_plan_device_bytes: bad argument");
+  *bytes = plan->exec.device_bytes();
+  return FPM_OK;
+}
+
+fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, float* intensity,
+                       fpm_mem where, void* hip_stream) {
+  if (!plan || !object || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_forward: NULL argument or bad memory kind");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_forward: cannot select the plan's device");
+  fpm_status st = ensure_setup(plan);
+  if (st != FPM_OK) return st;
+  Executor& ex = plan->exec;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t obj_bytes = sizeof(float2) * ex.total_obj;
+  const size_t pup_bytes = sizeof(float2) * ex.total_pupil;
+  const size_t int_bytes = sizeof(float) * ex.total_I;
+  const hipMemcpyKind h2d = where == FPM_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const float2* src = (const float2*)object;
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(hipMemcpyAsync(ex.obj_stage.p, object, obj_bytes, h2d, s), "H2D object", &st))
+      return st;
+    src = (const float2*)ex.obj_stage.p;
+  }
+  if (pupil) {
+    if (!hip_ok(hipMemcpyAsync(ex.fwd_P.p, pupil, pup_bytes, h2d, s), "copy pupil", &st)) return st;
+  } else if (!hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.fwd_P.p,
+                                   (const int64_t*)ex.p_off_d.p, 2, ex.n_max, s),
+                     "gather initial pupil", &st)) {
+    return st;
+  }
+  float* out = intensity;
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(ex.I_stage.alloc(int_bytes), "hipMalloc(intensity stage)", &st)) return st;
+    out = (float*)ex.I_stage.p;
+  }
+  if (!hip_ok(ex.enqueue_forward(src, out, s), "forward kernels", &st)) return st;
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(hipMemcpyAsync(intensity, out, int_bytes, hipMemcpyDeviceToHost, s), "D2H", &st) ||
+        !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st))
+      return st;
+  }
+  return FPM_OK;
+}
+
+fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem where,
+                           void* object_out, void* pupil_out, double* residual_out,
+                           void* hip_stream) {
+  if (!plan || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_reconstruct: NULL argument or bad memory kind");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_reconstruct: cannot select the plan's device");
+  fpm_status st = ensure_setup(plan);
+  if (st != FPM_OK) return st;
+  Executor& ex = plan->exec;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t int_bytes = sizeof(float) * ex.total_I;
+  const float* I = intensity;
+  if (where == FPM_MEM_HOST) {
+    for (int64_t i = 0; i < ex.total_I; ++i) {
+      const float v = intensity[i];
+      if (!(v >= 0.0f) || !std::isfinite(v))
+        return fail(FPM_E_ARG, "fpm_reconstruct: intensity " + std::to_string(i) +
+                                   " is negative or not finite");
+    }
+    if (!hip_ok(ex.I_stage.alloc(int_bytes), "hipMalloc(intensity stage)", &st) ||
+        !hip_ok(hipMemcpyAsync(ex.I_stage.p, intensity, int_bytes, hipMemcpyHostToDevice, s),
+                "H2D intensity", &st))
+      return st;
+    I = (const float*)ex.I_stage.p;
+  }
+  if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, I,
+                                   (const int64_t*)ex.i_off_d.p, s),
+              "set intensity", &st))
+    return st;
+  if (!hip_ok(ex.run(s, use_graphs()), "reconstruction sweep", &st)) return st;
+  const hipMemcpyKind d2o = where == FPM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (object_out) {
+    if (!hip_ok(ex.enqueue_finalize(s), "finalise", &st) ||
+        !hip_ok(hipMemcpyAsync(object_out, ex.obj_stage.p, sizeof(float2) * ex.total_obj, d2o, s),
+                "copy object", &st))
+      return st;
+  }
+  if (pupil_out) {
+    if (where == FPM_MEM_DEVICE) {
+      if (!hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, pupil_out,
+                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
+                  "gather pupil", &st))
+        return st;
+    } else {
+      if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
+          !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.pupil_stage.p,
+                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
+                  "gather pupil", &st) ||
+          !hip_ok(hipMemcpyAsync(pupil_out, ex.pupil_stage.p, sizeof(float2) * ex.total_pupil,
+                                 d2o, s),
+                  "copy pupil", &st))
+        return st;
+    }
+  }
+  std::vector<double> res_host;
+  const bool want_res_host = where == FPM_MEM_HOST;
+  if (residual_out || want_res_host) {
+    if (!hip_ok(ex.res_stage.alloc(sizeof(double) * std::max<int64_t>(1, ex.total_res)),
+                "hipMalloc", &st) ||
+        !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.res_stage.p,
+                              (const int64_t*)ex.r_off_d.p, 3, ex.n_max, s),
+                "gather residual", &st))
+      return st;
+    if (residual_out && where == FPM_MEM_DEVICE &&
+        !hip_ok(hipMemcpyAsync(residual_out, ex.res_stage.p, sizeof(double) * ex.total_res,
+                               hipMemcpyDeviceToDevice, s),
+                "copy residual", &st))
+      return st;
+    if (want_res_host) {
+      res_host.resize(std::max<int64_t>(1, ex.total_res));
+      if (!hip_ok(hipMemcpyAsync(res_host.data(), ex.res_stage.p, sizeof(double) * ex.total_res,
+                                 hipMemcpyDeviceToHost, s),
+                  "copy residual", &st))
+        return st;
+    }
+  }
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
+    for (int64_t i = 0; i < ex.total_res; ++i)
+      if (!std::isfinite(res_host[i]))
+        return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
+    if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
+  }
+  return FPM_OK;
+}
+
+}  // extern "C"

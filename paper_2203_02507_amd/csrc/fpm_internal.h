@@ -1,0 +1,108 @@
+// Internal declarations shared by the host plan, the executor and the HIP
+// kernels of libfpm.  Not part of the C ABI (include/fpm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fpm.h"
+
+namespace fpm {
+
+// ----------------------------------------------------------------- plan
+// Everything a tile needs that is fixed by its geometry (Sec. 2.2, Sec. 3.2).
+struct TilePlan {
+  fpm_tile_desc d{};
+  int n = 0, N = 0, L = 0;
+  int nd0 = 0;                       // |D0|
+  int kx0 = 0, nd = 0;               // support columns [kx0, kx0 + nd)
+  std::vector<uint8_t> mask;         // [n][n]
+  std::vector<int32_t> chord;        // [n][2]: rows [lo, hi] of column kx (lo > hi: empty)
+  std::vector<int32_t> off;          // [L][2] (drow, dcol)
+  std::vector<int32_t> order;        // [L] ascending illumination NA
+  std::vector<int32_t> group_of;     // [L]
+  std::vector<int32_t> sweep;        // [L] groups concatenated
+  std::vector<int32_t> gstart;       // [ngroups + 1]
+  int ngroups = 0, max_group = 0;
+  double min_tie = 0.0;
+  std::vector<float> pupil0;         // [n][n][2] complex64 initial pupil
+  // derived schedule: step s of an iteration updates LEDs steps[sbeg[s] .. sbeg[s+1])
+  std::vector<int32_t> step_leds, step_beg;
+  int nsteps = 0;
+  int64_t i_off = 0, o_off = 0, p_off = 0, r_off = 0;  // offsets in concatenated arrays
+};
+
+fpm_status build_tile_plan(const fpm_tile_desc& d, TilePlan& tp, std::string& err);
+
+// ------------------------------------------------------- device structures
+// Per-tile device view used by every kernel.  Plain pointers, no torch.
+struct TileDev {
+  float2* S;          // [N][N]  stored spectrum (true spectrum = sigma * S)
+  float2* P;          // [n][n]  pupil
+  const float* I;     // [L][n][n] intensities
+  float2* dP;         // [max_group][n][n] pupil increments of the current group
+  double* e_part;     // [L] residual numerator per LED, this iteration
+  double* i_part;     // [L] sum of I per LED, this iteration
+  double* sigma;      // [1] lazy spectrum scale
+  unsigned* smax;     // [1] bits of max |S|^2 (stored scale) at iteration start
+  const int2* chord;  // [n] (lo, hi) per support column
+  const float2* P0;   // [n][n] initial pupil
+  double* residual;   // [iterations]
+  int N, L, n, kx0, nd, nd0, j0, up;
+  int wy0_j0, wx0_j0;  // window of the initial spectrum (the centred window)
+  int mode;            // 0 spectrum only, 1 pupil in place, 2 pupil increments to dP
+  int iters;           // iterations of this tile
+};
+
+struct Item {      // one (tile, LED) update
+  int tile, led, wy0, wx0, slot, pad;
+};
+
+struct StepTile {  // a tile that ran a group in this step
+  int tile, count;
+};
+
+// Kernel launchers (kernels.hip).  All enqueue on `st` and return the HIP
+// status of the launch.
+hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
+                         hipStream_t st);
+hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
+                               float* out, const int64_t* out_off, int nd_max, hipStream_t st);
+hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
+                               hipStream_t st);
+hipError_t launch_iter_end(const TileDev* tiles, const int* tile_ids, int count, int iter,
+                           hipStream_t st);
+hipError_t launch_smax(const TileDev* tiles, const int* tile_ids, int count, int NN_max,
+                       hipStream_t st);
+hipError_t launch_init_state(const TileDev* tiles, const int* tile_ids, int count, int n,
+                             int N_max, hipStream_t st);
+// batched line FFTs over per-tile base pointers (see kernels.hip)
+struct LineJob {
+  float2* base;       // first element of line 0
+  int64_t line_stride, elem_stride;
+  int nlines;
+  float scale;        // applied to the output
+  int modulate;       // multiply output element (line l, elem e) by (-1)^(l+e)
+  int pad;
+};
+hipError_t launch_line_fft(const LineJob* jobs, int njobs, int len, int max_lines, int inverse,
+                           hipStream_t st);
+// dst[off[t] + i] = sigma * S * up^2 / N^2 for every tile (object finalise)
+hipError_t launch_scale_spectrum(const TileDev* tiles, int count, float2* dst, const int64_t* off,
+                                 int N_max, hipStream_t st);
+// obj_stage[t] = (-1)^(x+y) * object[t] / up^2 (ahead of the forward line FFTs)
+hipError_t launch_object_to_spectrum(const TileDev* tiles, int count, const float2* src_base,
+                                     const int64_t* src_off, int N_max, hipStream_t st);
+// table[t].I = base + i_off[t]   (kernel argument, so no host buffer outlives the call)
+hipError_t launch_set_intensity(TileDev* table, int count, const float* base,
+                                const int64_t* i_off, hipStream_t st);
+// dst[off[t] + i] = tile t's pupil (which = 1), initial pupil (which = 2) or
+// residual history (which = 3, doubles)
+hipError_t launch_gather(const TileDev* tiles, int count, void* dst, const int64_t* off,
+                         int which, int n_max, hipStream_t st);
+
+}  // namespace fpm

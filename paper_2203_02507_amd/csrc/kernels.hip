@@ -1,0 +1,859 @@
+// gfx950 kernels for the FPM alternating-projection sweep.
+//
+// Data path of one (tile, LED) update, one workgroup of 4n threads:
+//   phase A   gather X = sigma * S on the support columns, Phi = P X / n^2,
+//             IFFT along ky      (thread = (support column, quarter))
+//   LDS       transpose T[kx][y]
+//   phase B   IFFT along kx      (thread = (row y, quarter))
+//   modulus   psi' = sqrt(I) psi/|psi|, residual partials   (I prefetched)
+//   phase B'  FFT along x
+//   LDS       transpose U[kx][y] on the support columns only
+//   phase A'  FFT along y        (thread = (support column, quarter))
+//   update    S and P on the support pixels only
+// A length-n line FFT is split n = R * 4: each thread runs an R-point FFT
+// in registers; the 4 threads of a line combine with a radix-4 step done
+// as two radix-2 stages over DPP quad permutes (no LDS traffic).  The
+// centring shifts of the method are folded away: the inverse transform of
+// a centred spectrum equals the shifted one up to a (-1)^(x+y) factor,
+// which the modulus projection and the forward transform cancel exactly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "fpm_internal.h"
+
+namespace fpm {
+
+namespace {
+
+constexpr int kQ = 4;  // threads per line
+
+// ------------------------------------------------- compile-time twiddles
+constexpr double kPiD = 3.14159265358979323846;
+
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x2 / (double)((2 * i) * (2 * i + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x2 / (double)((2 * i - 1) * (2 * i));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi k / m, reduced to the first octant by exact integer
+// symmetry so the series stays on |x| <= pi/4.
+constexpr double cos2pi(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  // angle in units of 2pi/m; use 8k compared with m for octants
+  if (2 * k > m) return cos2pi(m - k, m);          // cos(2pi - a) = cos a
+  if (4 * k > m) return -cos2pi(m - 2 * k, 2 * m);  // a > pi/2: cos a = -cos(pi - a)
+  if (8 * k > m) return taylor_sin(2.0 * kPiD * (double)(m - 4 * k) / (4.0 * (double)m));
+  return taylor_cos(2.0 * kPiD * (double)k / (double)m);
+}
+constexpr double sin2pi(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  if (2 * k > m) return -sin2pi(m - k, m);         // sin(2pi - a) = -sin a
+  if (4 * k > m) return sin2pi(m - 2 * k, 2 * m);   // sin(pi - a) = sin a
+  if (8 * k > m) return taylor_cos(2.0 * kPiD * (double)(m - 4 * k) / (4.0 * (double)m));
+  return taylor_sin(2.0 * kPiD * (double)k / (double)m);
+}
+
+template <int M>
+struct TwTab {
+  float c[M], s[M];
+  constexpr TwTab() : c(), s() {
+    for (int k = 0; k < M; ++k) {
+      c[k] = (float)cos2pi(k, M);
+      s[k] = (float)sin2pi(k, M);
+    }
+  }
+};
+template <int M>
+__device__ constexpr TwTab<M> kTw{};
+
+// ------------------------------------------------------- complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// multiply by W_len^k (INV: exp(+2 pi i k/len), else exp(-2 pi i k/len));
+// k and len are compile-time after unrolling.
+template <int R, bool INV>
+__device__ __forceinline__ float2 tw_mul(float2 v, int k, int len) {
+  if (k == 0) return v;
+  if (4 * k == len) return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+  const int idx = k * (R / len);
+  const float c = kTw<R>.c[idx];
+  const float s = INV ? kTw<R>.s[idx] : -kTw<R>.s[idx];
+  return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// R-point FFT on registers, natural order in and out (R a power of two).
+template <int R, bool INV>
+__device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
+  constexpr int LB = ilog2(R);
+  float2 b[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) b[i] = a[bitrev(i, LB)];
+#pragma unroll
+  for (int half = 1; half < R; half *= 2) {
+#pragma unroll
+    for (int i = 0; i < R; i += 2 * half) {
+#pragma unroll
+      for (int k = 0; k < half; ++k) {
+        const float2 u = b[i + k];
+        const float2 v = tw_mul<R, INV>(b[i + k + half], k, 2 * half);
+        b[i + k] = cadd(u, v);
+        b[i + k + half] = csub(u, v);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = b[i];
+}
+
+// --------------------------------------------------- cross-lane radix-4
+// DPP quad permutes: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1].
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kXor1 = 0xB1;
+constexpr int kXor2 = 0x4E;
+
+// radix-2 stage with the partner lane (lane ^ M): lower lane a+b, upper a-b
+template <int CTRL>
+__device__ __forceinline__ float2 xstage(float2 v, float sgn) {
+  const float px = dpp<CTRL>(v.x), py = dpp<CTRL>(v.y);
+  return make_float2(fmaf(sgn, v.x, px), fmaf(sgn, v.y, py));
+}
+// lane 3 multiplies by W_4 (INV: +i, else -i)
+template <bool INV>
+__device__ __forceinline__ float2 w4_lane3(float2 v, bool is3) {
+  const float2 r = INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+  return is3 ? r : v;
+}
+
+// 4-point DFT across the 4 lanes of a line.  Input natural (lane q holds
+// x_q); output bit-reversed (lane q holds X_{brev2(q)}).
+template <bool INV, int R>
+__device__ __forceinline__ void xlane_nat2brev(float2 (&a)[R], int q) {
+  const float s2 = (q & 2) ? -1.0f : 1.0f, s1 = (q & 1) ? -1.0f : 1.0f;
+  const bool is3 = (q == 3);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    float2 v = xstage<kXor2>(a[i], s2);
+    v = w4_lane3<INV>(v, is3);
+    a[i] = xstage<kXor1>(v, s1);
+  }
+}
+// Input bit-reversed (lane q holds x_{brev2(q)}); output natural.
+template <bool INV, int R>
+__device__ __forceinline__ void xlane_brev2nat(float2 (&a)[R], int q) {
+  const float s2 = (q & 2) ? -1.0f : 1.0f, s1 = (q & 1) ? -1.0f : 1.0f;
+  const bool is3 = (q == 3);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    float2 v = xstage<kXor1>(a[i], s1);
+    v = w4_lane3<INV>(v, is3);
+    a[i] = xstage<kXor2>(v, s2);
+  }
+}
+
+__device__ __forceinline__ int brev2(int q) { return ((q & 1) << 1) | ((q >> 1) & 1); }
+
+// twiddle W_n^e from the LDS table tw[e] = exp(+2 pi i e / n)
+template <bool INV>
+__device__ __forceinline__ float2 lds_tw(const float2* tw, int e) {
+  const float2 w = tw[e];
+  return INV ? w : make_float2(w.x, -w.y);
+}
+
+// Line FFT, decimation in time.  In: lane q holds x[q + 4 p] in a[p].
+// Out: lane q holds X[R * brev2(q) + k] in a[k].
+template <int n, bool INV>
+__device__ __forceinline__ void line_dit(float2 (&a)[n / kQ], int q, const float2* tw) {
+  constexpr int R = n / kQ;
+  fft_reg<R, INV>(a);
+#pragma unroll
+  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], lds_tw<INV>(tw, q * k));
+  xlane_nat2brev<INV>(a, q);
+}
+// Line FFT, decimation in frequency.  In: lane q holds x[R * brev2(q) + m]
+// in a[m].  Out: lane q holds X[q + 4 k] in a[k].
+template <int n, bool INV>
+__device__ __forceinline__ void line_dif(float2 (&a)[n / kQ], int q, const float2* tw) {
+  constexpr int R = n / kQ;
+  xlane_brev2nat<INV>(a, q);
+#pragma unroll
+  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], lds_tw<INV>(tw, q * m));
+  fft_reg<R, INV>(a);
+}
+
+// Barrier that orders LDS only, so global loads in flight (the intensity
+// prefetch) are not drained at every phase boundary.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int n>
+constexpr int pitch() {
+  return n + 16;  // complex elements per LDS row (padding against bank conflicts)
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ------------------------------------------------ phase A: gather + IFFT
+// Thread (c, q) with c < nd: support column kx = kx0 + c, rows ky = q + 4p.
+// Returns the partial max |P|^2 of this thread's support pixels.
+template <int n>
+__device__ __forceinline__ float gather_phi(const TileDev& t, const Item& it, int c, int q,
+                                            float sig_over_n2, float2 (&a)[n / kQ]) {
+  constexpr int R = n / kQ;
+  const int kx = t.kx0 + c;
+  const int2 ch = t.chord[kx];
+  const float2* Scol = t.S + (size_t)it.wy0 * t.N + (it.wx0 + kx);
+  const float2* Pcol = t.P + kx;
+  float pm = 0.0f;
+#pragma unroll
+  for (int p = 0; p < R; ++p) {
+    const int ky = q + kQ * p;
+    if (ky >= ch.x && ky <= ch.y) {
+      const float2 x = Scol[(size_t)ky * t.N];
+      const float2 pv = Pcol[ky * n];
+      pm = fmaxf(pm, cabs2(pv));
+      a[p] = cscale(cmul(pv, x), sig_over_n2);
+    } else {
+      a[p] = make_float2(0.0f, 0.0f);
+    }
+  }
+  return pm;
+}
+
+// phase B input: lane q of row y takes kx = q + 4p from T[kx - kx0][y]
+template <int n>
+__device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, int y, int q,
+                                          float2 (&a)[n / kQ]) {
+  constexpr int R = n / kQ;
+#pragma unroll
+  for (int p = 0; p < R; ++p) {
+    const int c = q + kQ * p - kx0;
+    a[p] = (c >= 0 && c < nd) ? buf[c * pitch<n>() + y] : make_float2(0.0f, 0.0f);
+  }
+}
+
+}  // namespace
+
+// ===================================================== the update kernel
+// t.mode: 0 = spectrum only, 1 = pupil updated in place (one LED per tile in
+// the launch), 2 = pupil increment written to dP[slot] (LED groups).
+template <int n>
+__global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restrict__ tiles,
+                                                        const Item* __restrict__ items) {
+  constexpr int R = n / kQ;
+  constexpr int NT = n * kQ;
+  constexpr int NW = NT / 64;
+  extern __shared__ float2 sbuf[];  // [nd][pitch]
+  __shared__ float2 tw[n];
+  __shared__ float red_pmax[NW];
+  __shared__ double red_e[NW], red_i[NW];
+
+  const Item it = items[blockIdx.x];
+  const TileDev t = tiles[it.tile];
+  const int mode = t.mode;
+  const int tid = threadIdx.x;
+  const int q = tid & 3, line = tid >> 2;
+  const int wave = tid >> 6;
+
+  // twiddle table W_n^e = exp(+2 pi i e/n), correctly rounded at compile time
+  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+
+  // prefetch this thread's intensities for the modulus step: row `line`,
+  // columns [R*brev2(q), +R)
+  const int xc = R * brev2(q);
+  float ipre[R];
+  {
+    const float4* src =
+        reinterpret_cast<const float4*>(t.I + (size_t)it.led * n * n + (size_t)line * n + xc);
+#pragma unroll
+    for (int v = 0; v < R / 4; ++v) {
+      const float4 f = src[v];
+      ipre[4 * v] = f.x;
+      ipre[4 * v + 1] = f.y;
+      ipre[4 * v + 2] = f.z;
+      ipre[4 * v + 3] = f.w;
+    }
+  }
+
+  const double sigma = *t.sigma;
+  const float sigf = (float)sigma;
+  float2 a[R];
+  float pm = 0.0f;
+  lds_barrier();  // twiddles ready
+
+  // ---- phase A: support columns, IFFT along ky
+  if (line < t.nd) {
+    pm = gather_phi<n>(t, it, line, q, sigf / (float)(n * n), a);
+    line_dit<n, true>(a, q, tw);
+    float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
+#pragma unroll
+    for (int k = 0; k < R; ++k) dst[k] = a[k];
+  }
+  pm = wave_max(pm);
+  if ((tid & 63) == 0) red_pmax[wave] = pm;
+  lds_barrier();
+
+  // ---- phase B: rows, IFFT along kx
+  load_rows<n>(sbuf, t.kx0, t.nd, line, q, a);
+  lds_barrier();  // T fully consumed; the buffer is reused below
+  line_dit<n, true>(a, q, tw);
+
+  // ---- modulus constraint + residual partials (row `line`, x = xc + k)
+  float e_acc = 0.0f, i_acc = 0.0f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float I = ipre[k];
+    const float m = sqrtf(fmaxf(I, 0.0f));
+    const float amp = sqrtf(cabs2(a[k]));
+    const float d = amp - m;
+    e_acc = fmaf(d, d, e_acc);
+    i_acc += I;
+    a[k] = amp > 0.0f ? cscale(a[k], m / amp) : make_float2(m, 0.0f);
+  }
+  {
+    double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
+    if ((tid & 63) == 0) {
+      red_e[wave] = e;
+      red_i[wave] = s;
+    }
+  }
+
+  // ---- phase B': FFT along x (lane q holds x-chunk brev2(q))
+  line_dif<n, false>(a, q, tw);
+  // a[k] = row-transform at kx = q + 4k; keep the support columns only
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int c = q + kQ * k - t.kx0;
+    if (c >= 0 && c < t.nd) sbuf[c * pitch<n>() + line] = a[k];
+  }
+  lds_barrier();
+
+  // ---- phase A': support columns, FFT along y, then the update
+  if (line < t.nd) {
+    const float2* srcp = sbuf + line * pitch<n>() + R * brev2(q);
+#pragma unroll
+    for (int m = 0; m < R; ++m) a[m] = srcp[m];
+    line_dif<n, false>(a, q, tw);
+    // a[k] = Phi'(ky = q + 4k, kx)
+    float pmax2 = red_pmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
+    const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
+    const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
+    const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
+    const int kx = t.kx0 + line;
+    const int2 ch = t.chord[kx];
+    float2* Scol = t.S + (size_t)it.wy0 * t.N + (it.wx0 + kx);
+    float2* Pcol = t.P + kx;
+    float2* dPcol = t.dP + (size_t)it.slot * n * n + kx;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ky = q + kQ * k;
+      if (ky >= ch.x && ky <= ch.y) {
+        const float2 xs = Scol[(size_t)ky * t.N];   // stored spectrum
+        const float2 pv = Pcol[ky * n];
+        const float2 phi = cscale(cmul(pv, xs), sigf);
+        const float2 d = csub(a[k], phi);
+        // S_stored += conj(P) D / (max|P|^2 sigma)
+        if (pmax2 > 0.0f) Scol[(size_t)ky * t.N] = cadd(xs, cscale(cmulc(d, pv), inv_ps));
+        if (mode != 0 && smax > 0.0f) {
+          // dP = conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
+          const float2 dp = cscale(cmulc(d, xs), inv_ss);
+          if (mode == 1)
+            Pcol[ky * n] = cadd(pv, dp);
+          else
+            dPcol[ky * n] = dp;
+        } else if (mode == 2) {
+          dPcol[ky * n] = make_float2(0.0f, 0.0f);
+        }
+      }
+    }
+  }
+
+  if (tid == 0) {
+    double e = 0.0, s = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      e += red_e[w];
+      s += red_i[w];
+    }
+    t.e_part[it.led] = e;
+    t.i_part[it.led] = s;
+  }
+}
+
+// ================================================ forward model per LED
+// I_j = |IFFT_n(P * W_j(S))|^2 (the (-1)^(x+y) of the centring shift drops
+// out of the modulus).  sigma = 1, S is the object's scaled spectrum.
+template <int n>
+__global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restrict__ tiles,
+                                                         const Item* __restrict__ items,
+                                                         float* __restrict__ out,
+                                                         const int64_t* __restrict__ out_off) {
+  constexpr int R = n / kQ;
+  constexpr int NT = n * kQ;
+  extern __shared__ float2 sbuf[];
+  __shared__ float2 tw[n];
+  const Item it = items[blockIdx.x];
+  const TileDev t = tiles[it.tile];
+  const int tid = threadIdx.x;
+  const int q = tid & 3, line = tid >> 2;
+  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  lds_barrier();
+  float2 a[R];
+  if (line < t.nd) {
+    gather_phi<n>(t, it, line, q, 1.0f / (float)(n * n), a);
+    line_dit<n, true>(a, q, tw);
+    float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
+#pragma unroll
+    for (int k = 0; k < R; ++k) dst[k] = a[k];
+  }
+  lds_barrier();
+  load_rows<n>(sbuf, t.kx0, t.nd, line, q, a);
+  line_dit<n, true>(a, q, tw);
+  float4* dst = reinterpret_cast<float4*>(out + out_off[it.tile] + (size_t)it.led * n * n +
+                                          (size_t)line * n + R * brev2(q));
+#pragma unroll
+  for (int v = 0; v < R / 4; ++v)
+    dst[v] = make_float4(cabs2(a[4 * v]), cabs2(a[4 * v + 1]), cabs2(a[4 * v + 2]),
+                         cabs2(a[4 * v + 3]));
+}
+
+// ============================================== pupil mean of a group
+// P <- P + (1/count) sum_m dP[m] on D0, members summed in slot order.
+__global__ __launch_bounds__(256) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
+                                                           const StepTile* __restrict__ steps) {
+  const StepTile s = steps[blockIdx.y];
+  const TileDev t = tiles[s.tile];
+  const int n = t.n;
+  const int px = blockIdx.x * 256 + threadIdx.x;
+  if (px >= n * n) return;
+  const int ky = px / n, kx = px % n;
+  const int2 ch = t.chord[kx];
+  if (ky < ch.x || ky > ch.y) return;
+  float2 acc = make_float2(0.0f, 0.0f);
+  for (int m = 0; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * n * n + px]);
+  t.P[px] = cadd(t.P[px], cscale(acc, 1.0f / (float)s.count));
+}
+
+// ============================================ end of an iteration (FP64)
+// residual = sum_j e_j / sum_j I_j (LEDs in grid order); with pupil
+// recovery: s = sqrt(|D0| / sum_D0 |P|^2), P <- s P, sigma <- sigma / s.
+// Also clears the running spectrum maximum for the next iteration.
+__global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict__ tiles,
+                                                       const int* __restrict__ ids, int iter) {
+  const TileDev t = tiles[ids[blockIdx.x]];
+  const int pupil_update = t.mode != 0;
+  const int tid = threadIdx.x;
+  __shared__ double r0[256], r1[256];
+  __shared__ double s_scale;
+  double e = 0.0, s = 0.0;
+  for (int j = tid; j < t.L; j += 256) {
+    e += t.e_part[j];
+    s += t.i_part[j];
+  }
+  r0[tid] = e;
+  r1[tid] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      r0[tid] += r0[tid + o];
+      r1[tid] += r1[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) t.residual[iter] = r1[0] > 0.0 ? r0[0] / r1[0] : 0.0;
+  __syncthreads();
+  if (pupil_update) {
+    const int n = t.n;
+    double E = 0.0;
+    for (int px = tid; px < n * n; px += 256) {
+      const int ky = px / n, kx = px % n;
+      const int2 ch = t.chord[kx];
+      if (ky >= ch.x && ky <= ch.y) {
+        const float2 p = t.P[px];
+        E += (double)p.x * (double)p.x + (double)p.y * (double)p.y;
+      }
+    }
+    r0[tid] = E;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) r0[tid] += r0[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double sc = r0[0] > 0.0 ? sqrt((double)t.nd0 / r0[0]) : 1.0;
+      s_scale = sc;
+      *t.sigma = *t.sigma / sc;
+    }
+    __syncthreads();
+    const float sc = (float)s_scale;
+    for (int px = tid; px < n * n; px += 256) t.P[px] = cscale(t.P[px], sc);
+  }
+  if (tid == 0) *t.smax = 0u;
+}
+
+// max |S_stored|^2 over the whole spectrum (order-free: max of non-negative
+// floats via their bit patterns)
+__global__ __launch_bounds__(256) void smax_kernel(const TileDev* __restrict__ tiles,
+                                                   const int* __restrict__ ids) {
+  const TileDev t = tiles[ids[blockIdx.y]];
+  const size_t NN = (size_t)t.N * t.N;
+  float m = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN; i += (size_t)gridDim.x * 256)
+    m = fmaxf(m, cabs2(t.S[i]));
+  m = wave_max(m);
+  __shared__ float wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float v = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    atomicMax(t.smax, __float_as_uint(v));
+  }
+}
+
+// initial state: S = 0 except the centred window <- (-1)^(x+y) sqrt(I_j0) (its
+// 2-D FFT follows as line FFTs), P = P_init, sigma = 1, smax = 0
+__global__ __launch_bounds__(256) void init_state_kernel(const TileDev* __restrict__ tiles,
+                                                         const int* __restrict__ ids) {
+  const TileDev t = tiles[ids[blockIdx.y]];
+  const size_t NN = (size_t)t.N * t.N;
+  const int n = t.n;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN; i += (size_t)gridDim.x * 256) {
+    const int r = (int)(i / t.N), c = (int)(i % t.N);
+    const int u = r - t.wy0_j0, v = c - t.wx0_j0;
+    float2 val = make_float2(0.0f, 0.0f);
+    if (u >= 0 && u < n && v >= 0 && v < n) {
+      const float I = t.I[(size_t)t.j0 * n * n + (size_t)u * n + v];
+      const float m = sqrtf(fmaxf(I, 0.0f));
+      val = make_float2(((u + v) & 1) ? -m : m, 0.0f);
+    }
+    t.S[i] = val;
+  }
+  if (blockIdx.x == 0) {
+    for (int px = threadIdx.x; px < n * n; px += 256) t.P[px] = t.P0[px];
+    if (threadIdx.x == 0) {
+      *t.sigma = 1.0;
+      *t.smax = 0u;
+    }
+  }
+}
+
+// ======================================================= line FFTs
+// One workgroup per line: load into LDS, Stockham passes of radix 4/2/3/5,
+// store with an optional scale and (-1)^(line+elem) modulation.
+namespace {
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2, bool inv) {
+  const float s = inv ? 0.86602540378443864676f : -0.86602540378443864676f;
+  const float2 t1 = cadd(a1, a2), t2 = csub(a1, a2);
+  const float2 m1 = make_float2(a0.x - 0.5f * t1.x, a0.y - 0.5f * t1.y);
+  const float2 m2 = make_float2(-s * t2.y, s * t2.x);
+  a0 = cadd(a0, t1);
+  a1 = cadd(m1, m2);
+  a2 = csub(m1, m2);
+}
+__device__ __forceinline__ void dft5(float2 (&v)[5], bool inv) {
+  float2 o[5];
+  for (int k = 0; k < 5; ++k) {
+    float2 acc = v[0];
+    for (int j = 1; j < 5; ++j) {
+      const int e = (j * k) % 5;
+      const float c = kTw<5>.c[e], s = inv ? kTw<5>.s[e] : -kTw<5>.s[e];
+      acc = cadd(acc, make_float2(v[j].x * c - v[j].y * s, v[j].x * s + v[j].y * c));
+    }
+    o[k] = acc;
+  }
+  for (int k = 0; k < 5; ++k) v[k] = o[k];
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void line_fft_kernel(const LineJob* __restrict__ jobs, int len,
+                                                       int inverse) {
+  const LineJob job = jobs[blockIdx.y];
+  const int line = blockIdx.x;
+  if (line >= job.nlines) return;
+  extern __shared__ float2 lbuf[];
+  float2* x = lbuf;
+  float2* y = lbuf + len;
+  float2* base = job.base + (size_t)line * job.line_stride;
+  for (int i = threadIdx.x; i < len; i += 256) x[i] = base[(size_t)i * job.elem_stride];
+  __syncthreads();
+  const float sgn = inverse ? 1.0f : -1.0f;
+  int ns = 1;
+  int rem = len;
+  while (rem > 1) {
+    int r = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
+    const int m = len / r;
+    for (int j = threadIdx.x; j < m; j += 256) {
+      const int k = j % ns;
+      float2 v[5];
+      for (int q = 0; q < r; ++q) {
+        float2 e = x[j + q * m];
+        if (q > 0 && k > 0) {  // twiddle in FP64, rounded once
+          double s, c;
+          sincospi((double)sgn * 2.0 * (double)(k * q) / (double)(ns * r), &s, &c);
+          e = cmul(e, make_float2((float)c, (float)s));
+        }
+        v[q] = e;
+      }
+      if (r == 2) {
+        const float2 t0 = v[0];
+        v[0] = cadd(t0, v[1]);
+        v[1] = csub(t0, v[1]);
+      } else if (r == 4) {
+        const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const float2 b0 = cadd(v[1], v[3]), b1d = csub(v[1], v[3]);
+        const float2 b1 = inverse ? make_float2(-b1d.y, b1d.x) : make_float2(b1d.y, -b1d.x);
+        v[0] = cadd(a0, b0);
+        v[2] = csub(a0, b0);
+        v[1] = cadd(a1, b1);
+        v[3] = csub(a1, b1);
+      } else if (r == 3) {
+        dft3(v[0], v[1], v[2], inverse);
+      } else {
+        dft5(v, inverse);
+      }
+      const int d = (j / ns) * ns * r + k;
+      for (int q = 0; q < r; ++q) y[d + q * ns] = v[q];
+    }
+    __syncthreads();
+    float2* tmp = x;
+    x = y;
+    y = tmp;
+    ns *= r;
+    rem /= r;
+  }
+  for (int i = threadIdx.x; i < len; i += 256) {
+    float2 v = cscale(x[i], job.scale);
+    if (job.modulate && ((line + i) & 1)) v = make_float2(-v.x, -v.y);
+    base[(size_t)i * job.elem_stride] = v;
+  }
+}
+
+// dst[off[t] + i] = sigma * S * up^2 / N^2   (object finalise, before the
+// inverse line FFTs)
+__global__ __launch_bounds__(256) void scale_spectrum_kernel(const TileDev* __restrict__ tiles,
+                                                             float2* __restrict__ dst,
+                                                             const int64_t* __restrict__ off) {
+  const TileDev t = tiles[blockIdx.y];
+  float2* out = dst + off[blockIdx.y];
+  const size_t NN = (size_t)t.N * t.N;
+  const float sc = (float)(*t.sigma * (double)t.up * (double)t.up / (double)NN);
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN; i += (size_t)gridDim.x * 256)
+    out[i] = cscale(t.S[i], sc);
+}
+
+// which = 1: pupil, 2: initial pupil (complex64 [n][n]); 3: residual (double)
+__global__ __launch_bounds__(256) void gather_kernel(const TileDev* __restrict__ tiles,
+                                                     void* __restrict__ dst,
+                                                     const int64_t* __restrict__ off, int which) {
+  const TileDev t = tiles[blockIdx.y];
+  if (which == 3) {
+    double* out = (double*)dst + off[blockIdx.y];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < t.iters; i += gridDim.x * 256)
+      out[i] = t.residual[i];
+    return;
+  }
+  float2* out = (float2*)dst + off[blockIdx.y];
+  const float2* src = which == 1 ? t.P : t.P0;
+  const int nn = t.n * t.n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nn; i += gridDim.x * 256) out[i] = src[i];
+}
+
+// S = (-1)^(x+y) * object / up^2 into the tile's spectrum buffer
+__global__ __launch_bounds__(256) void obj_mod_kernel(const TileDev* __restrict__ tiles,
+                                                      const float2* __restrict__ src,
+                                                      const int64_t* __restrict__ src_off) {
+  const TileDev t = tiles[blockIdx.y];
+  const int N = t.N;
+  const size_t NN = (size_t)N * N;
+  const float2* s = src + src_off[blockIdx.y];
+  const float sc = 1.0f / (float)(t.up * t.up);
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN; i += (size_t)gridDim.x * 256) {
+    const int r = (int)(i / N), c = (int)(i % N);
+    t.S[i] = cscale(s[i], ((r + c) & 1) ? -sc : sc);
+  }
+}
+
+__global__ void set_intensity_kernel(TileDev* __restrict__ table, int count,
+                                     const float* __restrict__ base,
+                                     const int64_t* __restrict__ i_off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) table[t].I = base + i_off[t];
+}
+
+// ========================================================== launchers
+namespace {
+template <int n>
+size_t update_lds(int nd_max) {
+  return (size_t)nd_max * pitch<n>() * sizeof(float2);
+}
+template <int n>
+hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
+                           hipStream_t st) {
+  const size_t lds = update_lds<n>(nd_max);
+  hipLaunchKernelGGL(update_kernel<n>, dim3(count), dim3(n * kQ), lds, st, tiles, items);
+  return hipGetLastError();
+}
+template <int n>
+hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, float* out,
+                            const int64_t* off, int nd_max, hipStream_t st) {
+  const size_t lds = update_lds<n>(nd_max);
+  hipLaunchKernelGGL(forward_kernel<n>, dim3(count), dim3(n * kQ), lds, st, tiles, items, out,
+                     off);
+  return hipGetLastError();
+}
+bool g_attr_done = false;
+void set_lds_limits() {
+  if (g_attr_done) return;
+  g_attr_done = true;
+  const int big = 160 * 1024 - 4096;
+  (void)hipFuncSetAttribute((const void*)update_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)forward_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)forward_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
+                         hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  set_lds_limits();
+  switch (n) {
+    case 64: return launch_update_n<64>(tiles, items, count, nd_max, st);
+    case 128: return launch_update_n<128>(tiles, items, count, nd_max, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
+                               float* out, const int64_t* out_off, int nd_max, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  set_lds_limits();
+  switch (n) {
+    case 64: return launch_forward_n<64>(tiles, items, count, out, out_off, nd_max, st);
+    case 128: return launch_forward_n<128>(tiles, items, count, out, out_off, nd_max, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
+                               hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n * n + 255) / 256, count), dim3(256), 0, st,
+                     tiles, steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_iter_end(const TileDev* tiles, const int* ids, int count, int iter,
+                           hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iter_end_kernel, dim3(count), dim3(256), 0, st, tiles, ids, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_smax(const TileDev* tiles, const int* ids, int count, int NN_max,
+                       hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int chunks = (NN_max + 256 * 16 - 1) / (256 * 16);
+  hipLaunchKernelGGL(smax_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const TileDev* tiles, const int* ids, int count, int /*n*/,
+                             int N_max, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int chunks = ((size_t)N_max * N_max + 256 * 16 - 1) / (256 * 16);
+  hipLaunchKernelGGL(init_state_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_line_fft(const LineJob* jobs, int njobs, int len, int max_lines, int inverse,
+                           hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const size_t lds = (size_t)2 * len * sizeof(float2);
+  hipLaunchKernelGGL(line_fft_kernel, dim3(max_lines, njobs), dim3(256), lds, st, jobs, len,
+                     inverse);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_spectrum(const TileDev* tiles, int count, float2* dst, const int64_t* off,
+                                 int N_max, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int chunks = (int)(((size_t)N_max * N_max + 256 * 16 - 1) / (256 * 16));
+  hipLaunchKernelGGL(scale_spectrum_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, dst, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const TileDev* tiles, int count, void* dst, const int64_t* off, int which,
+                         int n_max, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int chunks = which == 3 ? 1 : (n_max * n_max + 255) / 256;
+  hipLaunchKernelGGL(gather_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, dst, off, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_object_to_spectrum(const TileDev* tiles, int count, const float2* src_base,
+                                     const int64_t* src_off, int N_max, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int chunks = (int)(((size_t)N_max * N_max + 256 * 16 - 1) / (256 * 16));
+  hipLaunchKernelGGL(obj_mod_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, src_base, src_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_intensity(TileDev* table, int count, const float* base, const int64_t* i_off,
+                                hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_intensity_kernel, dim3((count + 255) / 256), dim3(256), 0, st, table, count,
+                     base, i_off);
+  return hipGetLastError();
+}
+
+}  // namespace fpm

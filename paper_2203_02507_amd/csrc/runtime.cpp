@@ -1,0 +1,503 @@
+// Executor and C ABI for plans: device state, work lists, hipGraph capture
+// and replay of the reconstruction sweep, the forward model.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fpm_internal.h"
+#include "runtime.h"
+
+namespace fpm {
+
+thread_local std::string g_last_error;
+
+fpm_status fail(fpm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool hip_ok(hipError_t e, const char* what, fpm_status* st) {
+  if (e == hipSuccess) return true;
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  *st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FPM_E_NOMEM : FPM_E_DEVICE;
+  return false;
+}
+
+// ------------------------------------------------------------- DevBuf
+DevBuf::~DevBuf() {
+  if (p) hipFree(p);
+}
+hipError_t DevBuf::alloc(size_t n) {
+  if (p && bytes >= n) return hipSuccess;
+  if (p) hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&p, n);
+  if (e == hipSuccess) bytes = n;
+  return e;
+}
+
+// ------------------------------------------------------------ Executor
+Executor::~Executor() {
+  if (graph_exec) hipGraphExecDestroy(graph_exec);
+  if (cap_stream) hipStreamDestroy(cap_stream);
+}
+
+namespace {
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
+  fpm_status st = FPM_OK;
+  const int T = (int)tiles.size();
+  // ---- persistent per-tile state, one allocation
+  struct Lay {
+    int64_t S, P, dP, e, i, sig, smax, chord, P0, res;
+  };
+  std::vector<Lay> lay(T);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  for (int t = 0; t < T; ++t) {
+    const TilePlan& tp = tiles[t];
+    const int64_t nn = (int64_t)tp.n * tp.n, NN = (int64_t)tp.N * tp.N;
+    const bool grouped = tp.d.schedule == FPM_SCHED_LED_GROUPS && tp.d.pupil_update;
+    lay[t].S = take(NN * 8);
+    lay[t].P = take(nn * 8);
+    lay[t].dP = take((grouped ? tp.max_group : 1) * nn * 8);
+    lay[t].e = take((int64_t)tp.L * 8);
+    lay[t].i = take((int64_t)tp.L * 8);
+    lay[t].sig = take(8);
+    lay[t].smax = take(4);
+    lay[t].chord = take((int64_t)tp.n * 8);
+    lay[t].P0 = take(nn * 8);
+    lay[t].res = take((int64_t)std::max(1, tp.d.iterations) * 8);
+  }
+  if (!hip_ok(state.alloc((size_t)off), "hipMalloc(state)", &st)) return st;
+  char* base = (char*)state.p;
+  host_tiles.assign(T, TileDev{});
+  for (int t = 0; t < T; ++t) {
+    const TilePlan& tp = tiles[t];
+    TileDev& d = host_tiles[t];
+    d.S = (float2*)(base + lay[t].S);
+    d.P = (float2*)(base + lay[t].P);
+    d.I = nullptr;
+    d.dP = (float2*)(base + lay[t].dP);
+    d.e_part = (double*)(base + lay[t].e);
+    d.i_part = (double*)(base + lay[t].i);
+    d.sigma = (double*)(base + lay[t].sig);
+    d.smax = (unsigned*)(base + lay[t].smax);
+    d.chord = (const int2*)(base + lay[t].chord);
+    d.P0 = (const float2*)(base + lay[t].P0);
+    d.residual = (double*)(base + lay[t].res);
+    d.N = tp.N;
+    d.L = tp.L;
+    d.n = tp.n;
+    d.kx0 = tp.kx0;
+    d.nd = tp.nd;
+    d.nd0 = tp.nd0;
+    d.up = tp.d.upsample;
+    const int j0 = tp.step_leds.empty() ? 0 : tp.step_leds[0];
+    d.j0 = j0;
+    d.wy0_j0 = tp.N / 2 - tp.n / 2;  // initial spectrum: the centred window
+    d.wx0_j0 = tp.N / 2 - tp.n / 2;
+    d.mode = !tp.d.pupil_update ? 0 : (tp.d.schedule == FPM_SCHED_LED_GROUPS ? 2 : 1);
+    d.iters = tp.d.iterations;
+    // static tables
+    if (!hip_ok(hipMemcpy((void*)d.chord, tp.chord.data(), (size_t)tp.n * 8, hipMemcpyHostToDevice),
+                "hipMemcpy(chord)", &st))
+      return st;
+    if (!hip_ok(hipMemcpy((void*)d.P0, tp.pupil0.data(), (size_t)tp.n * tp.n * 8,
+                          hipMemcpyHostToDevice),
+                "hipMemcpy(P0)", &st))
+      return st;
+  }
+  if (!hip_ok(table.alloc(sizeof(TileDev) * T), "hipMalloc(table)", &st)) return st;
+
+  // ---- work lists
+  std::vector<Item> items;
+  std::vector<StepTile> steptiles;
+  std::vector<int> ids;
+  launches.clear();
+  int max_iter = 0, max_steps = 0;
+  std::map<int, int> nclass;  // n -> max nd
+  for (const TilePlan& tp : tiles) {
+    max_iter = std::max(max_iter, tp.d.iterations);
+    max_steps = std::max(max_steps, tp.nsteps);
+    nclass[tp.n] = std::max(nclass[tp.n], tp.nd);
+  }
+  for (auto& kv : nclass)
+    if (kv.first == 96) return fail(FPM_E_UNSUPPORTED, "n = 96 kernels are not built yet");
+  int maxN = 0;
+  for (const TilePlan& tp : tiles) maxN = std::max(maxN, tp.N);
+  NN_max = maxN * maxN;
+
+  auto id_range = [&](const std::vector<int>& v) {
+    Launch r{};
+    r.off = (int)ids.size();
+    r.count = (int)v.size();
+    ids.insert(ids.end(), v.begin(), v.end());
+    return r;
+  };
+  // init
+  {
+    std::vector<int> all(T);
+    for (int t = 0; t < T; ++t) all[t] = t;
+    Launch l = id_range(all);
+    l.kind = Launch::INIT;
+    launches.push_back(l);
+    init_ids = l;
+  }
+  std::vector<int> prev_active;
+  int reuse_from = -1;  // first launch index of the previous iteration body
+  for (int k = 0; k < max_iter; ++k) {
+    std::vector<int> active;
+    for (int t = 0; t < T; ++t)
+      if (tiles[t].d.iterations > k) active.push_back(t);
+    const int body_start = (int)launches.size();
+    if (k > 0 && active == prev_active && reuse_from >= 0) {
+      // identical work lists: replay the previous iteration's launches
+      const int body_len = body_start - reuse_from;
+      for (int i = 0; i < body_len; ++i) {
+        Launch l = launches[reuse_from + i];
+        if (l.kind == Launch::ITER_END) l.iter = k;
+        if (l.kind == Launch::SMAX && k + 1 >= max_iter) {
+          bool any = false;
+          for (int t : active) any |= tiles[t].d.iterations > k + 1;
+          if (!any) continue;
+        }
+        launches.push_back(l);
+      }
+      reuse_from = body_start;
+      prev_active = active;
+      continue;
+    }
+    for (int s = 0; s < max_steps; ++s) {
+      for (auto& kv : nclass) {
+        Launch l{};
+        l.kind = Launch::UPDATE;
+        l.n = kv.first;
+        l.nd_max = kv.second;
+        l.off = (int)items.size();
+        for (int t : active) {
+          const TilePlan& tp = tiles[t];
+          if (tp.n != kv.first || s >= tp.nsteps) continue;
+          for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
+            const int j = tp.step_leds[m];
+            Item it{};
+            it.tile = t;
+            it.led = j;
+            it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+            it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+            it.slot = m - tp.step_beg[s];
+            items.push_back(it);
+          }
+        }
+        l.count = (int)items.size() - l.off;
+        if (l.count > 0) launches.push_back(l);
+      }
+      // pupil means of the groups that ran in this step
+      Launch r{};
+      r.kind = Launch::REDUCE;
+      r.off = (int)steptiles.size();
+      int nmax = 0;
+      for (int t : active) {
+        const TilePlan& tp = tiles[t];
+        if (host_tiles[t].mode != 2 || s >= tp.nsteps) continue;
+        steptiles.push_back(StepTile{t, tp.step_beg[s + 1] - tp.step_beg[s]});
+        nmax = std::max(nmax, tp.n);
+      }
+      r.count = (int)steptiles.size() - r.off;
+      r.n = nmax;
+      if (r.count > 0) launches.push_back(r);
+    }
+    Launch e = id_range(active);
+    e.kind = Launch::ITER_END;
+    e.iter = k;
+    launches.push_back(e);
+    std::vector<int> next;
+    for (int t : active)
+      if (tiles[t].d.iterations > k + 1) next.push_back(t);
+    if (!next.empty()) {
+      Launch m = id_range(next);
+      m.kind = Launch::SMAX;
+      launches.push_back(m);
+    }
+    reuse_from = body_start;
+    prev_active = active;
+  }
+  total_updates = 0;
+  for (const TilePlan& tp : tiles) total_updates += (int64_t)tp.d.iterations * tp.L;
+
+  if (!hip_ok(items_d.alloc(std::max<size_t>(1, items.size()) * sizeof(Item)), "hipMalloc(items)",
+              &st))
+    return st;
+  if (!items.empty() &&
+      !hip_ok(hipMemcpy(items_d.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice),
+              "hipMemcpy(items)", &st))
+    return st;
+  if (!hip_ok(steps_d.alloc(std::max<size_t>(1, steptiles.size()) * sizeof(StepTile)),
+              "hipMalloc(steps)", &st))
+    return st;
+  if (!steptiles.empty() &&
+      !hip_ok(hipMemcpy(steps_d.p, steptiles.data(), steptiles.size() * sizeof(StepTile),
+                        hipMemcpyHostToDevice),
+              "hipMemcpy(steps)", &st))
+    return st;
+  if (!hip_ok(ids_d.alloc(std::max<size_t>(1, ids.size()) * sizeof(int)), "hipMalloc(ids)", &st))
+    return st;
+  if (!ids.empty() &&
+      !hip_ok(hipMemcpy(ids_d.p, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice),
+              "hipMemcpy(ids)", &st))
+    return st;
+
+  // ---- line-FFT jobs for the initial window (rows, then columns), per n
+  std::vector<LineJob> jobs;
+  init_line_launches.clear();
+  for (auto& kv : nclass) {
+    for (int pass = 0; pass < 2; ++pass) {
+      LineLaunch ll{};
+      ll.off = (int)jobs.size();
+      ll.len = kv.first;
+      ll.inverse = 0;
+      for (int t = 0; t < T; ++t) {
+        if (tiles[t].n != kv.first) continue;
+        const TileDev& d = host_tiles[t];
+        LineJob j{};
+        j.base = d.S + (size_t)d.wy0_j0 * d.N + d.wx0_j0;
+        j.line_stride = pass == 0 ? d.N : 1;
+        j.elem_stride = pass == 0 ? 1 : d.N;
+        j.nlines = d.n;
+        j.scale = 1.0f;
+        j.modulate = 0;
+        jobs.push_back(j);
+      }
+      ll.count = (int)jobs.size() - ll.off;
+      ll.max_lines = kv.first;
+      init_line_launches.push_back(ll);
+    }
+  }
+
+  // ---- concatenated-array offsets
+  {
+    std::vector<int64_t> io(T), oo(T), po(T), ro(T);
+    total_I = total_obj = total_pupil = total_res = 0;
+    n_max = 0;
+    for (int t = 0; t < T; ++t) {
+      const TilePlan& tp = tiles[t];
+      io[t] = total_I;
+      oo[t] = total_obj;
+      po[t] = total_pupil;
+      ro[t] = total_res;
+      total_I += (int64_t)tp.L * tp.n * tp.n;
+      total_obj += (int64_t)tp.N * tp.N;
+      total_pupil += (int64_t)tp.n * tp.n;
+      total_res += tp.d.iterations;
+      n_max = std::max(n_max, tp.n);
+    }
+    for (auto* pr : {&i_off_d, &o_off_d, &p_off_d, &r_off_d})
+      if (!hip_ok(pr->alloc(sizeof(int64_t) * T), "hipMalloc(offsets)", &st)) return st;
+    if (!hip_ok(hipMemcpy(i_off_d.p, io.data(), 8 * T, hipMemcpyHostToDevice), "hipMemcpy", &st) ||
+        !hip_ok(hipMemcpy(o_off_d.p, oo.data(), 8 * T, hipMemcpyHostToDevice), "hipMemcpy", &st) ||
+        !hip_ok(hipMemcpy(p_off_d.p, po.data(), 8 * T, hipMemcpyHostToDevice), "hipMemcpy", &st) ||
+        !hip_ok(hipMemcpy(r_off_d.p, ro.data(), 8 * T, hipMemcpyHostToDevice), "hipMemcpy", &st))
+      return st;
+    if (!hip_ok(obj_stage.alloc(sizeof(float2) * total_obj), "hipMalloc(object stage)", &st) ||
+        !hip_ok(fwd_P.alloc(sizeof(float2) * total_pupil), "hipMalloc(pupil stage)", &st))
+      return st;
+    // finalise (inverse, on obj_stage) and forward (forward, on obj_stage) line jobs per N
+    std::map<int, std::vector<int>> byN;
+    for (int t = 0; t < T; ++t) byN[tiles[t].N].push_back(t);
+    float2* ob = (float2*)obj_stage.p;
+    for (int inv = 1; inv >= 0; --inv) {
+      auto& dstl = inv ? fin_line_launches : fwd_line_launches;
+      dstl.clear();
+      for (auto& kv : byN) {
+        for (int pass = 0; pass < 2; ++pass) {
+          LineLaunch ll{};
+          ll.off = (int)jobs.size();
+          ll.len = kv.first;
+          ll.inverse = inv;
+          ll.max_lines = kv.first;
+          for (int t : kv.second) {
+            LineJob j{};
+            j.base = ob + oo[t];
+            j.line_stride = pass == 0 ? kv.first : 1;
+            j.elem_stride = pass == 0 ? 1 : kv.first;
+            j.nlines = kv.first;
+            j.scale = 1.0f;
+            j.modulate = (inv && pass == 1) ? 1 : 0;
+            jobs.push_back(j);
+          }
+          ll.count = (int)jobs.size() - ll.off;
+          dstl.push_back(ll);
+        }
+      }
+    }
+    // forward-model table: spectrum in obj_stage, pupil in fwd_P
+    std::vector<TileDev> ft = host_tiles;
+    for (int t = 0; t < T; ++t) {
+      ft[t].S = ob + oo[t];
+      ft[t].P = (float2*)fwd_P.p + po[t];
+    }
+    if (!hip_ok(fwd_table.alloc(sizeof(TileDev) * T), "hipMalloc(fwd table)", &st) ||
+        !hip_ok(hipMemcpy(fwd_table.p, ft.data(), sizeof(TileDev) * T, hipMemcpyHostToDevice),
+                "hipMemcpy(fwd table)", &st))
+      return st;
+    std::vector<Item> fi;
+    fwd_launches.clear();
+    for (auto& kv : nclass) {
+      FwdLaunch fl{kv.first, kv.second, (int)fi.size(), 0};
+      for (int t = 0; t < T; ++t) {
+        const TilePlan& tp = tiles[t];
+        if (tp.n != kv.first) continue;
+        for (int j = 0; j < tp.L; ++j) {
+          Item it{};
+          it.tile = t;
+          it.led = j;
+          it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+          it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+          fi.push_back(it);
+        }
+      }
+      fl.count = (int)fi.size() - fl.off;
+      fwd_launches.push_back(fl);
+    }
+    if (!hip_ok(fwd_items.alloc(sizeof(Item) * std::max<size_t>(1, fi.size())), "hipMalloc", &st) ||
+        !hip_ok(hipMemcpy(fwd_items.p, fi.data(), sizeof(Item) * fi.size(), hipMemcpyHostToDevice),
+                "hipMemcpy(fwd items)", &st))
+      return st;
+  }
+  if (!hip_ok(hipMemcpy(table.p, host_tiles.data(), sizeof(TileDev) * T, hipMemcpyHostToDevice),
+              "hipMemcpy(table)", &st))
+    return st;
+  if (!hip_ok(jobs_d.alloc(std::max<size_t>(1, jobs.size()) * sizeof(LineJob)), "hipMalloc(jobs)",
+              &st))
+    return st;
+  if (!jobs.empty() &&
+      !hip_ok(hipMemcpy(jobs_d.p, jobs.data(), jobs.size() * sizeof(LineJob), hipMemcpyHostToDevice),
+              "hipMemcpy(jobs)", &st))
+    return st;
+  ntiles = T;
+  ready = true;
+  return FPM_OK;
+}
+
+hipError_t Executor::enqueue_sweep(hipStream_t s) {
+  const TileDev* tab = (const TileDev*)table.p;
+  const Item* it = (const Item*)items_d.p;
+  const StepTile* stp = (const StepTile*)steps_d.p;
+  const int* ids = (const int*)ids_d.p;
+  const LineJob* jobs = (const LineJob*)jobs_d.p;
+  hipError_t e = hipSuccess;
+  for (const Launch& l : launches) {
+    switch (l.kind) {
+      case Launch::INIT: {
+        e = launch_init_state(tab, ids + l.off, l.count, 0, (int)std::sqrt((double)NN_max), s);
+        for (const LineLaunch& ll : init_line_launches) {
+          if (e != hipSuccess) break;
+          e = launch_line_fft(jobs + ll.off, ll.count, ll.len, ll.max_lines, ll.inverse, s);
+        }
+        if (e == hipSuccess) e = launch_smax(tab, ids + l.off, l.count, (int)NN_max, s);
+        break;
+      }
+      case Launch::UPDATE:
+        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, s);
+        break;
+      case Launch::REDUCE:
+        e = launch_pupil_reduce(tab, stp + l.off, l.count, l.n, s);
+        break;
+      case Launch::ITER_END:
+        e = launch_iter_end(tab, ids + l.off, l.count, l.iter, s);
+        break;
+      case Launch::SMAX:
+        e = launch_smax(tab, ids + l.off, l.count, (int)NN_max, s);
+        break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+hipError_t Executor::run(hipStream_t s, bool use_graph) {
+  if (!use_graph) return enqueue_sweep(s);
+  if (!graph_exec) {
+    hipError_t e;
+    if (!cap_stream) {
+      e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue_sweep(cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap_stream, &g);
+    if (le != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      graph_exec = nullptr;
+      return e;
+    }
+  }
+  return hipGraphLaunch(graph_exec, s);
+}
+
+}  // namespace fpm
+
+namespace fpm {
+
+hipError_t Executor::enqueue_finalize(hipStream_t s) {
+  const TileDev* tab = (const TileDev*)table.p;
+  const LineJob* jobs = (const LineJob*)jobs_d.p;
+  const int Nmax = (int)std::lround(std::sqrt((double)NN_max));
+  hipError_t e = launch_scale_spectrum(tab, ntiles, (float2*)obj_stage.p, (const int64_t*)o_off_d.p,
+                                       Nmax, s);
+  for (const LineLaunch& ll : fin_line_launches) {
+    if (e != hipSuccess) return e;
+    e = launch_line_fft(jobs + ll.off, ll.count, ll.len, ll.max_lines, ll.inverse, s);
+  }
+  return e;
+}
+
+hipError_t Executor::enqueue_forward(const float2* obj_src, float* out, hipStream_t s) {
+  const TileDev* ft = (const TileDev*)fwd_table.p;
+  const LineJob* jobs = (const LineJob*)jobs_d.p;
+  const int Nmax = (int)std::lround(std::sqrt((double)NN_max));
+  hipError_t e = launch_object_to_spectrum(ft, ntiles, obj_src, (const int64_t*)o_off_d.p, Nmax, s);
+  for (const LineLaunch& ll : fwd_line_launches) {
+    if (e != hipSuccess) return e;
+    e = launch_line_fft(jobs + ll.off, ll.count, ll.len, ll.max_lines, ll.inverse, s);
+  }
+  for (const FwdLaunch& fl : fwd_launches) {
+    if (e != hipSuccess) return e;
+    e = launch_forward_leds(fl.n, ft, (const Item*)fwd_items.p + fl.off, fl.count, out,
+                            (const int64_t*)i_off_d.p, fl.nd_max, s);
+  }
+  return e;
+}
+
+size_t Executor::device_bytes() const {
+  const DevBuf* all[] = {&state, &table, &items_d, &steps_d, &ids_d, &jobs_d, &i_off_d, &o_off_d,
+                         &p_off_d, &r_off_d, &obj_stage, &fwd_P, &fwd_table, &fwd_items,
+                         &I_stage, &res_stage, &pupil_stage};
+  size_t b = 0;
+  for (const DevBuf* d : all) b += d->bytes;
+  return b;
+}
+
+}  // namespace fpm

@@ -1,0 +1,76 @@
+// Executor: device state and the launch sequence of a reconstruction.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fpm_internal.h"
+
+namespace fpm {
+
+extern thread_local std::string g_last_error;
+fpm_status fail(fpm_status s, const std::string& msg);
+bool hip_ok(hipError_t e, const char* what, fpm_status* st);
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  hipError_t alloc(size_t n);  // (re)allocate to at least n bytes; contents undefined
+};
+
+struct Launch {
+  enum Kind { INIT, UPDATE, REDUCE, ITER_END, SMAX } kind = INIT;
+  int n = 0, nd_max = 0;   // UPDATE: tile side, largest support-column count
+  int off = 0, count = 0;  // range in the item / step-tile / tile-id lists
+  int iter = 0;            // ITER_END
+};
+
+struct LineLaunch {
+  int off = 0, count = 0, len = 0, max_lines = 0, inverse = 0;
+};
+
+// Everything one plan needs on the device to run the sweep of all its tiles:
+// per-tile state (spectrum, pupil, scratch, residual partials), the work
+// lists of every launch, and the captured graph that replays them.
+struct Executor {
+  bool ready = false;
+  int ntiles = 0;
+  int64_t NN_max = 0;
+  int64_t total_updates = 0;
+  DevBuf state, table, items_d, steps_d, ids_d, jobs_d;
+  std::vector<TileDev> host_tiles;
+  std::vector<Launch> launches;
+  std::vector<LineLaunch> init_line_launches;
+  Launch init_ids;
+  // concatenated-array offsets per tile (device copies): intensity, object,
+  // pupil, residual
+  DevBuf i_off_d, o_off_d, p_off_d, r_off_d;
+  int64_t total_I = 0, total_obj = 0, total_pupil = 0, total_res = 0;
+  int n_max = 0;
+  // object finalise / forward staging: complex [total_obj], pupil [total_pupil]
+  DevBuf obj_stage, fwd_P, fwd_table, fwd_items, I_stage, res_stage, pupil_stage;
+  std::vector<LineLaunch> fin_line_launches, fwd_line_launches;
+  struct FwdLaunch {
+    int n, nd_max, off, count;
+  };
+  std::vector<FwdLaunch> fwd_launches;
+  const float* I_bound = nullptr;  // intensity base the table currently points at
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
+  ~Executor();
+  fpm_status setup(const std::vector<TilePlan>& tiles);
+  hipError_t enqueue_sweep(hipStream_t s);
+  hipError_t run(hipStream_t s, bool use_graph);
+  // object_stage <- up^2 IFFT_N(shift(sigma S)) for every tile
+  hipError_t enqueue_finalize(hipStream_t s);
+  // intensities for every (tile, LED) from obj_stage spectra and fwd_P
+  hipError_t enqueue_forward(const float2* obj_src, float* out, hipStream_t s);
+  size_t device_bytes() const;
+};
+
+}  // namespace fpm

@@ -1,0 +1,123 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every declared
+symbol is exported, and the plan's integer tables (spectrum offsets, order,
+LED groups) equal the FP64 oracle's bit for bit."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import fpm_synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fpm():
+    import paper_2203_02507_amd as fpm
+    return fpm
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fpm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpm_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(fpm):
+    names = declared_functions()
+    assert len(names) >= 15
+    out = subprocess.check_output(["nm", "-D", "--defined-only", fpm.LIB_PATH]).decode()
+    exported = set(re.findall(r"\bT (fpm_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+    assert set(fpm.EXPORTS) == set(names)
+    for n in names:
+        getattr(fpm.lib, n)
+
+
+def _check_tables(fpm, orc, descs):
+    plan = fpm.Plan(descs)
+    for t, d in enumerate(descs):
+        off, order, gof, sweep = plan.tables(t)
+        st, ooff = orc.offsets(d)
+        assert st == 0
+        assert np.array_equal(off, ooff)
+        assert np.array_equal(order, orc.order(d))
+        G = orc.groups(d)
+        assert np.array_equal(gof, G.group_of)
+        assert np.array_equal(sweep, G.sweep)
+        info = plan.infos[t]
+        assert info.ngroups == G.count
+        assert info.max_group == int(np.diff(G.gstart).max())
+        assert info.support_count == orc.support(d)[1]
+        assert info.min_tie_distance > 1e-9
+    return plan
+
+
+def test_plan_matches_oracle_single_tile(fpm, orc):
+    d = fpm_synth.single_tile_64()[0].desc
+    plan = _check_tables(fpm, orc, [d])
+    assert plan.infos[0].ngroups == 27 and plan.infos[0].support_count == 1201
+    assert plan.infos[0].steps == 225            # sequential: one LED per step
+
+
+def test_plan_matches_oracle_full_field(fpm, orc):
+    descs = [td.desc for td in fpm_synth.full_fov_tiles()]
+    for d in descs[::5]:
+        d.defocus_um = 7.5
+    plan = _check_tables(fpm, orc, descs[::3])
+    assert all(i.steps == i.ngroups for i in plan.infos)   # grouped schedule
+    tie = min(fpm.Plan(descs).tile_info(t).min_tie_distance for t in range(256))
+    assert 1e-9 < tie < 1e-4          # the full field has a value close to a .5 tie
+
+
+def test_plan_matches_oracle_uneven(fpm, orc):
+    descs = []
+    for td in fpm_synth.uneven_batch(T=64):
+        if td.desc.n == 256:
+            continue
+        for up in td.up_candidates:
+            td.desc.upsample = up
+            if orc.offsets(td.desc)[0] == 0:
+                break
+        else:
+            continue
+        descs.append(td.desc)
+    assert len(descs) > 20
+    _check_tables(fpm, orc, descs)
+
+
+def test_plan_errors(fpm):
+    d = fpm_synth.TileDesc(n=64, upsample=3, led_rows=21, led_cols=21)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([d])
+    assert e.value.status == fpm.FPM_E_GEOMETRY
+    bad = fpm_synth.TileDesc(n=64, upsample=4, wavelength_um=-1.0)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([bad])
+    assert e.value.status == fpm.FPM_E_ARG
+    odd = fpm_synth.TileDesc(n=60, upsample=4)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([odd])
+    assert e.value.status == fpm.FPM_E_UNSUPPORTED
+    nyq = fpm_synth.TileDesc(n=64, upsample=4, na_obj=0.2)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([nyq])
+    assert e.value.status == fpm.FPM_E_ARG
+    with pytest.raises(fpm.FpmError):
+        fpm.Plan([])
+
+
+def test_host_mode_rejects_bad_intensities_without_gpu_work(fpm):
+    """Validation happens on the host before any device call."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("covered by the GPU tests")
+    # without a GPU the call must fail cleanly (device or argument error), never crash
+    d = fpm_synth.single_tile_64(iterations=1)[0].desc
+    plan = fpm.Plan([d])
+    I = np.ones((225, 64, 64), np.float32)
+    I[3, 2, 1] = np.nan
+    with pytest.raises(fpm.FpmError):
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_HOST)
