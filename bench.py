@@ -1,0 +1,213 @@
+"""Benchmark: LED-tile updates per second of the full reconstruction.
+
+Workload (default): the full field of view of a 2048 x 2048 sensor cut into
+16 x 16 overlapping tiles of 128 px (8 px overlap), each with its own
+illumination angles (tile position) and defocus z ~ U[-20, 20] um, 15 x 15
+LEDs (4 mm pitch, 90 mm high), 4x upsampling (512 x 512 spectrum per tile),
+20 iterations, LED groups run concurrently (spectrum-domain parallel form),
+pupil recovery on, FP32 FFT path.  One step = one complete reconstruction
+of all 256 tiles = 256 * 225 * 20 = 1,152,000 LED-tile updates, with the
+intensity stack already resident in HBM.
+
+Inputs are synthetic and seeded (fpm_synth): per-tile objects, the forward
+model run by the library itself, Poisson noise at 1e4 peak photons drawn
+with a seeded torch generator on the device.
+
+Prints one JSON line (rank 0): metric, value, roofline of the update kernel
+(HIP events per launch), the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_2203_02507_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernel_128_traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def make_inputs(fpm, tds, device):
+    """Objects (numpy, seeded) -> library forward model -> Poisson noise."""
+    import numpy as np
+    import torch
+    import fpm_synth
+
+    descs = []
+    objs = []
+    for td in tds:
+        objs.append(fpm_synth.draw_object_and_defocus(td, 20.0).astype(np.complex64))
+        descs.append(td.desc)
+    plan = fpm.Plan(descs)
+    o = torch.from_numpy(np.concatenate([x.reshape(-1) for x in objs]).view(np.float32)).to(device)
+    del objs
+    I = torch.empty(plan.total_intensity, dtype=torch.float32, device=device)
+    fpm.fpm_forward(plan, o, None, I, fpm.FPM_MEM_DEVICE)
+    torch.cuda.synchronize()
+    del o
+    gen = torch.Generator(device=device)
+    gen.manual_seed(fpm_synth.ROOT_SEED)
+    for t, info in enumerate(plan.infos):
+        sl = I[info.intensity_offset:info.intensity_offset + info.L * info.n * info.n]
+        c = tds[t].peak_photons / float(sl.max())
+        sl.copy_(torch.poisson(sl.clamp_min(0) * c, generator=gen) / c)
+    torch.cuda.synchronize()
+    return plan, I
+
+
+def roofline(plan, prof):
+    """Algorithmic HBM bytes of the update kernel per launch / mean launch time.
+
+    Per LED-tile update: read the intensity image (4 n^2 B), read and write
+    the support pixels of the spectrum window (2 * 8 |D0| B)."""
+    upd = prof["update"]
+    info = plan.infos[0]
+    b_upd = 4 * info.n * info.n + 16 * info.support_count
+    per_launch_items = upd["items"] / max(upd["launches"], 1)
+    mean_s = upd["total_ms"] / 1e3 / max(upd["launches"], 1)
+    achieved = b_upd * per_launch_items / mean_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        if rec.get("kernel_sha256_16") == kernel_hash():
+            traffic = rec.get("hbm_bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"update_kernel<{info.n}>", "bytes_per_update": b_upd,
+            "updates_per_launch": round(per_launch_items, 1),
+            "mean_launch_us": round(mean_s * 1e6, 2)}
+
+
+def cpu_baseline(n_tiles: int = 8):
+    """FP64 oracle on a bounded sample: the first `n_tiles` tiles of the
+    same workload, one iteration each, one tile per host thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    import fpm_synth
+    import oracle
+
+    tds = fpm_synth.full_fov_tiles(only=list(range(n_tiles)))
+    threads = max(1, min(n_tiles, os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(threads) as ex:
+        inputs = list(ex.map(lambda td: oracle.synthesize(td, z_range=20.0)[2], tds))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(lambda a: oracle.reconstruct(a[0].desc, a[1], iterations=1),
+                          zip(tds, inputs)))
+    wall = time.perf_counter() - t0
+    assert all(r.status == 0 for r in res)
+    updates = n_tiles * tds[0].desc.L
+    return {"value": round(updates / wall, 2), "unit": "updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_tiles} tiles x 1 iteration x 225 LEDs of the 128-px full-field "
+                      f"workload ({updates} updates, {wall:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tiles-per-side", type=int, default=16)
+    ap.add_argument("--iterations", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (tiles are "
+              "independent, so a multi-GPU run would shard tiles across GPUs).", file=sys.stderr)
+        sys.exit(2)
+    if args.no_graph:
+        os.environ["FPM_NO_GRAPH"] = "1"
+
+    import torch
+    import fpm_synth
+    import paper_2203_02507_amd as fpm
+
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+    tds = fpm_synth.full_fov_tiles(tiles_per_side=args.tiles_per_side, iterations=args.iterations,
+                                   schedule=fpm.FPM_SCHED_LED_GROUPS, pupil_update=1)
+    t0 = time.perf_counter()
+    plan, I = make_inputs(fpm, tds, device)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {len(tds)} tiles, "
+        f"{I.numel() * 4 / 2**30:.2f} GiB of intensities on the device")
+    obj, pup, res = fpm.device_buffers(plan, device)
+    updates = sum(i.L * i.iterations for i in plan.infos)
+
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, obj, pup, res)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = ev_ms / args.steps
+    value = updates * args.steps / (ev_ms / 1e3)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step (events), wall {wall:.3f} s")
+    r = res.cpu().numpy()
+    if not all(math.isfinite(x) for x in r):
+        raise SystemExit("non-finite residual")
+
+    prof = fpm.fpm_profile_reconstruct(plan, I)
+    torch.cuda.synchronize()
+    log("kernel time per kind: " + json.dumps(prof))
+    roof = roofline(plan, prof)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    info = plan.infos[0]
+    out = {
+        "metric": "LED-tile updates/sec (FP32 FFT path)",
+        "value": round(value, 1),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"full-field {args.tiles_per_side}x{args.tiles_per_side} tiles of "
+                        f"{info.n} px, 15x15 LEDs, {info.N}x{info.N} spectrum per tile, "
+                        f"{args.iterations} iterations, LED groups, pupil recovery, FP32 FFT",
+            "tiles": plan.ntiles, "n": info.n, "N": info.N, "leds": info.L,
+            "iterations": args.iterations, "updates_per_step": updates,
+            "schedule": "led_groups", "precision": "fp32_fft",
+            "graph": not args.no_graph,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

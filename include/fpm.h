@@ -179,6 +179,31 @@ fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem whe
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
 
+/* Per-kind kernel timing of one reconstruction (profiling aid). */
+typedef enum {
+  FPM_KERNEL_UPDATE = 0,      /* fused LED-tile update (the hot loop)          */
+  FPM_KERNEL_PUPIL_MEAN = 1,  /* mean pupil increment of an LED group          */
+  FPM_KERNEL_ITER_END = 2,    /* FP64 residual + pupil-energy normalisation    */
+  FPM_KERNEL_SPEC_MAX = 3,    /* max |S|^2 for the next iteration's pupil step */
+  FPM_KERNEL_INIT = 4,        /* initial state and its FFT                      */
+  FPM_KERNEL_KINDS = 5
+} fpm_kernel_kind;
+
+typedef struct {
+  int32_t launches;   /* kernel launches of this kind                      */
+  int32_t pad;
+  int64_t items;      /* FPM_KERNEL_UPDATE: LED-tile updates processed      */
+  double total_ms;    /* sum of per-launch durations (HIP events)           */
+} fpm_kernel_time;
+
+/* Run the reconstruction sweep of `plan` once, eagerly (no graph), with a
+ * HIP event pair around every launch on `hip_stream`; synchronise; fill
+ * out[FPM_KERNEL_KINDS].  Same kernels and launch shapes as
+ * fpm_reconstruct; the state it leaves is that of a reconstruction.
+ * `intensity` as in fpm_reconstruct with FPM_MEM_DEVICE. */
+fpm_status fpm_profile_reconstruct(fpm_plan_t *plan, const float *intensity,
+                                   fpm_kernel_time *out, void *hip_stream);
+
 /* ------------------------------------------------------------ serving */
 
 typedef struct {

@@ -38,7 +38,7 @@ STATUS_NAMES = {0: "FPM_OK", 1: "FPM_PENDING", -1: "FPM_E_ARG", -2: "FPM_E_GEOME
 EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_tables",
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
-           "fpm_last_error", "fpm_version")
+           "fpm_last_error", "fpm_version", "fpm_profile_reconstruct")
 
 
 class FpmError(RuntimeError):
@@ -69,6 +69,14 @@ class TileInfoC(C.Structure):
         ("intensity_offset", C.c_int64), ("object_offset", C.c_int64),
         ("pupil_offset", C.c_int64), ("residual_offset", C.c_int64),
     ]
+
+
+class KernelTimeC(C.Structure):
+    _fields_ = [("launches", C.c_int32), ("pad", C.c_int32), ("items", C.c_int64),
+                ("total_ms", C.c_double)]
+
+
+KERNEL_KINDS = ("update", "pupil_mean", "iter_end", "spec_max", "init")
 
 
 class RequestStatsC(C.Structure):
@@ -108,6 +116,8 @@ def _load():
     L.fpm_wait.restype = C.c_int
     L.fpm_cancel.argtypes = [vp, C.c_uint64]
     L.fpm_cancel.restype = C.c_int
+    L.fpm_profile_reconstruct.argtypes = [vp, vp, C.POINTER(KernelTimeC), vp]
+    L.fpm_profile_reconstruct.restype = C.c_int
     L.fpm_last_error.argtypes = []
     L.fpm_last_error.restype = C.c_char_p
     L.fpm_version.argtypes = []
@@ -252,6 +262,15 @@ def fpm_reconstruct(plan: Plan, intensity, where: int, object_out=None, pupil_ou
     return check(lib.fpm_reconstruct(plan.handle, _ptr(intensity, where), where,
                                      _ptr(object_out, where), _ptr(pupil_out, where),
                                      _ptr(residual_out, where), _stream(stream)))
+
+
+def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:
+    """Per-kind kernel time of one eager reconstruction sweep (HIP events)."""
+    out = (KernelTimeC * len(KERNEL_KINDS))()
+    check(lib.fpm_profile_reconstruct(plan.handle, _ptr(intensity, FPM_MEM_DEVICE), out,
+                                      _stream(stream)))
+    return {name: {"launches": out[i].launches, "items": out[i].items,
+                   "total_ms": out[i].total_ms} for i, name in enumerate(KERNEL_KINDS)}
 
 
 def version() -> str:

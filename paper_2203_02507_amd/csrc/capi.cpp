@@ -267,4 +267,22 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   return FPM_OK;
 }
 
+fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
+                                   fpm_kernel_time* out, void* hip_stream) {
+  if (!plan || !intensity || !out) return fail(FPM_E_ARG, "fpm_profile_reconstruct: NULL argument");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_profile_reconstruct: cannot select the plan's device");
+  fpm_status st = ensure_setup(plan);
+  if (st != FPM_OK) return st;
+  Executor& ex = plan->exec;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, intensity,
+                                   (const int64_t*)ex.i_off_d.p, s),
+              "set intensity", &st) ||
+      !hip_ok(ex.profile(s, out), "profiled sweep", &st))
+    return st;
+  return FPM_OK;
+}
+
 }  // extern "C"

@@ -393,6 +393,48 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   return FPM_OK;
 }
 
+hipError_t Executor::profile(hipStream_t s, fpm_kernel_time* out) {
+  for (int k = 0; k < FPM_KERNEL_KINDS; ++k) out[k] = fpm_kernel_time{};
+  std::vector<hipEvent_t> ev(2 * launches.size() + 2, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) break;
+  std::vector<int> kinds;
+  std::vector<int64_t> nitems;
+  size_t used = 0;
+  if (e == hipSuccess) {
+    // one launch of the sweep at a time, bracketed by events
+    std::vector<Launch> saved = launches;
+    for (size_t i = 0; i < saved.size() && e == hipSuccess; ++i) {
+      launches.assign(1, saved[i]);
+      e = hipEventRecord(ev[used], s);
+      if (e == hipSuccess) e = enqueue_sweep(s);
+      if (e == hipSuccess) e = hipEventRecord(ev[used + 1], s);
+      used += 2;
+      const Launch& l = saved[i];
+      kinds.push_back(l.kind == Launch::UPDATE     ? FPM_KERNEL_UPDATE
+                      : l.kind == Launch::REDUCE   ? FPM_KERNEL_PUPIL_MEAN
+                      : l.kind == Launch::ITER_END ? FPM_KERNEL_ITER_END
+                      : l.kind == Launch::SMAX     ? FPM_KERNEL_SPEC_MAX
+                                                   : FPM_KERNEL_INIT);
+      nitems.push_back(l.kind == Launch::UPDATE ? l.count : 0);
+    }
+    launches = saved;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (size_t i = 0; e == hipSuccess && i < kinds.size(); ++i) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+    fpm_kernel_time& k = out[kinds[i]];
+    k.launches += 1;
+    k.items += nitems[i];
+    k.total_ms += ms;
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return e;
+}
+
 hipError_t Executor::enqueue_sweep(hipStream_t s) {
   const TileDev* tab = (const TileDev*)table.p;
   const Item* it = (const Item*)items_d.p;

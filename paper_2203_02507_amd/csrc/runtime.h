@@ -66,6 +66,8 @@ struct Executor {
   fpm_status setup(const std::vector<TilePlan>& tiles);
   hipError_t enqueue_sweep(hipStream_t s);
   hipError_t run(hipStream_t s, bool use_graph);
+  // eager sweep with an event pair around each launch; per-kind totals
+  hipError_t profile(hipStream_t s, fpm_kernel_time* out);
   // object_stage <- up^2 IFFT_N(shift(sigma S)) for every tile
   hipError_t enqueue_finalize(hipStream_t s);
   // intensities for every (tile, LED) from obj_stage spectra and fwd_P
