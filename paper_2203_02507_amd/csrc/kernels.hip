@@ -140,8 +140,9 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
 // DPP quad permutes: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1].
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  // every lane of a quad reads a valid partner, so no "old" value is needed
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 constexpr int kXor1 = 0xB1;
 constexpr int kXor2 = 0x4E;
@@ -223,6 +224,28 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Raw buffer access: an offset at or beyond the record count reads 0 and
+// drops a store, which turns the support-disc predicates into a select on
+// the offset instead of a branch per element.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kOob = 0x7FFFFFF0;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, int off) {
+  const v2f v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, float2 x) {
+  v2f v;
+  v.x = x.x;
+  v.y = x.y;
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
 template <int n>
 constexpr int pitch() {
   return n + 16;  // complex elements per LDS row (padding against bank conflicts)
@@ -242,27 +265,23 @@ __device__ __forceinline__ float wave_max(float v) {
 
 // ------------------------------------------------ phase A: gather + IFFT
 // Thread (c, q) with c < nd: support column kx = kx0 + c, rows ky = q + 4p.
+// Sw / Pw: buffer views of the LED's spectrum window and of the pupil.
 // Returns the partial max |P|^2 of this thread's support pixels.
 template <int n>
-__device__ __forceinline__ float gather_phi(const TileDev& t, const Item& it, int c, int q,
-                                            float sig_over_n2, float2 (&a)[n / kQ]) {
+__device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_buffer_rsrc_t Pw,
+                                            int N, int kx, int2 ch, int q, float scale,
+                                            float2 (&a)[n / kQ]) {
   constexpr int R = n / kQ;
-  const int kx = t.kx0 + c;
-  const int2 ch = t.chord[kx];
-  const float2* Scol = t.S + (size_t)it.wy0 * t.N + (it.wx0 + kx);
-  const float2* Pcol = t.P + kx;
   float pm = 0.0f;
+  const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
     const int ky = q + kQ * p;
-    if (ky >= ch.x && ky <= ch.y) {
-      const float2 x = Scol[(size_t)ky * t.N];
-      const float2 pv = Pcol[ky * n];
-      pm = fmaxf(pm, cabs2(pv));
-      a[p] = cscale(cmul(pv, x), sig_over_n2);
-    } else {
-      a[p] = make_float2(0.0f, 0.0f);
-    }
+    const bool in = ky >= ch.x && ky <= ch.y;
+    const float2 xs = bload2(Sw, in ? s0 + p * (kQ * 8) * N : kOob);
+    const float2 pv = bload2(Pw, in ? p0 + p * (kQ * 8 * n) : kOob);
+    pm = fmaxf(pm, cabs2(pv));
+    a[p] = cscale(cmul(pv, xs), scale);
   }
   return pm;
 }
@@ -301,6 +320,15 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   const int tid = threadIdx.x;
   const int q = tid & 3, line = tid >> 2;
   const int wave = tid >> 6;
+  const int N = t.N;
+
+  // buffer views: this LED's spectrum window, the pupil, its intensity image,
+  // the pupil-increment slot
+  const size_t woff = (size_t)it.wy0 * N + it.wx0;
+  const __amdgpu_buffer_rsrc_t Sw = make_rsrc(t.S + woff, (unsigned)(((size_t)N * N - woff) * 8));
+  const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
+  const __amdgpu_buffer_rsrc_t Iw = make_rsrc(t.I + (size_t)it.led * n * n, n * n * 4);
+  const __amdgpu_buffer_rsrc_t Dw = make_rsrc(t.dP + (size_t)it.slot * n * n, n * n * 8);
 
   // twiddle table W_n^e = exp(+2 pi i e/n), correctly rounded at compile time
   for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
@@ -309,28 +337,26 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   // columns [R*brev2(q), +R)
   const int xc = R * brev2(q);
   float ipre[R];
-  {
-    const float4* src =
-        reinterpret_cast<const float4*>(t.I + (size_t)it.led * n * n + (size_t)line * n + xc);
 #pragma unroll
-    for (int v = 0; v < R / 4; ++v) {
-      const float4 f = src[v];
-      ipre[4 * v] = f.x;
-      ipre[4 * v + 1] = f.y;
-      ipre[4 * v + 2] = f.z;
-      ipre[4 * v + 3] = f.w;
-    }
+  for (int v = 0; v < R / 4; ++v) {
+    const v4f f = __builtin_amdgcn_raw_buffer_load_b128(Iw, (line * n + xc + 4 * v) * 4, 0, 0);
+    ipre[4 * v] = f.x;
+    ipre[4 * v + 1] = f.y;
+    ipre[4 * v + 2] = f.z;
+    ipre[4 * v + 3] = f.w;
   }
 
-  const double sigma = *t.sigma;
-  const float sigf = (float)sigma;
+  const float sigf = (float)*t.sigma;
   float2 a[R];
   float pm = 0.0f;
+  const bool col_line = line < t.nd;
+  const int kx = t.kx0 + (col_line ? line : 0);
+  const int2 ch = col_line ? t.chord[kx] : make_int2(n, -1);
   lds_barrier();  // twiddles ready
 
   // ---- phase A: support columns, IFFT along ky
-  if (line < t.nd) {
-    pm = gather_phi<n>(t, it, line, q, sigf / (float)(n * n), a);
+  if (col_line) {
+    pm = gather_phi<n>(Sw, Pw, N, kx, ch, q, sigf / (float)(n * n), a);
     line_dit<n, true>(a, q, tw);
     float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
 #pragma unroll
@@ -350,12 +376,15 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
-    const float m = sqrtf(fmaxf(I, 0.0f));
-    const float amp = sqrtf(cabs2(a[k]));
+    const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+    const float p2 = cabs2(a[k]);
+    const float rinv = p2 > 0.0f ? __builtin_amdgcn_rsqf(p2) : 0.0f;
+    const float amp = p2 * rinv;
     const float d = amp - m;
     e_acc = fmaf(d, d, e_acc);
     i_acc += I;
-    a[k] = amp > 0.0f ? cscale(a[k], m / amp) : make_float2(m, 0.0f);
+    const float s = m * rinv;
+    a[k] = p2 > 0.0f ? cscale(a[k], s) : make_float2(m, 0.0f);
   }
   {
     double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
@@ -376,7 +405,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   lds_barrier();
 
   // ---- phase A': support columns, FFT along y, then the update
-  if (line < t.nd) {
+  if (col_line) {
     const float2* srcp = sbuf + line * pitch<n>() + R * brev2(q);
 #pragma unroll
     for (int m = 0; m < R; ++m) a[m] = srcp[m];
@@ -388,31 +417,27 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
     const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
     const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
     const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
-    const int kx = t.kx0 + line;
-    const int2 ch = t.chord[kx];
-    float2* Scol = t.S + (size_t)it.wy0 * t.N + (it.wx0 + kx);
-    float2* Pcol = t.P + kx;
-    float2* dPcol = t.dP + (size_t)it.slot * n * n + kx;
+    const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
+    const bool upd_s = pmax2 > 0.0f;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int ky = q + kQ * k;
-      if (ky >= ch.x && ky <= ch.y) {
-        const float2 xs = Scol[(size_t)ky * t.N];   // stored spectrum
-        const float2 pv = Pcol[ky * n];
-        const float2 phi = cscale(cmul(pv, xs), sigf);
-        const float2 d = csub(a[k], phi);
-        // S_stored += conj(P) D / (max|P|^2 sigma)
-        if (pmax2 > 0.0f) Scol[(size_t)ky * t.N] = cadd(xs, cscale(cmulc(d, pv), inv_ps));
-        if (mode != 0 && smax > 0.0f) {
-          // dP = conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
-          const float2 dp = cscale(cmulc(d, xs), inv_ss);
-          if (mode == 1)
-            Pcol[ky * n] = cadd(pv, dp);
-          else
-            dPcol[ky * n] = dp;
-        } else if (mode == 2) {
-          dPcol[ky * n] = make_float2(0.0f, 0.0f);
-        }
+      const bool in = ky >= ch.x && ky <= ch.y;
+      const int offS = in ? s0 + k * (kQ * 8) * N : kOob;
+      const int offP = in ? p0 + k * (kQ * 8 * n) : kOob;
+      const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
+      const float2 pv = bload2(Pw, offP);
+      const float2 phi = cscale(cmul(pv, xs), sigf);
+      const float2 d = csub(a[k], phi);
+      // S_stored += conj(P) D / (max|P|^2 sigma)
+      bstore2(Sw, upd_s ? offS : kOob, cadd(xs, cscale(cmulc(d, pv), inv_ps)));
+      if (mode != 0) {
+        // dP = conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
+        const float2 dp = cscale(cmulc(d, xs), inv_ss);
+        if (mode == 1)
+          bstore2(Pw, offP, cadd(pv, dp));
+        else
+          bstore2(Dw, offP, dp);
       }
     }
   }
@@ -448,7 +473,12 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
   lds_barrier();
   float2 a[R];
   if (line < t.nd) {
-    gather_phi<n>(t, it, line, q, 1.0f / (float)(n * n), a);
+    const size_t woff = (size_t)it.wy0 * t.N + it.wx0;
+    const __amdgpu_buffer_rsrc_t Sw =
+        make_rsrc(t.S + woff, (unsigned)(((size_t)t.N * t.N - woff) * 8));
+    const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
+    const int kx = t.kx0 + line;
+    gather_phi<n>(Sw, Pw, t.N, kx, t.chord[kx], q, 1.0f / (float)(n * n), a);
     line_dit<n, true>(a, q, tw);
     float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
 #pragma unroll
@@ -467,19 +497,22 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 
 // ============================================== pupil mean of a group
 // P <- P + (1/count) sum_m dP[m] on D0, members summed in slot order.
-__global__ __launch_bounds__(256) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
+// Block (c, tile): support column kx0 + c; thread: a row of its chord.
+__global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
                                                            const StepTile* __restrict__ steps) {
   const StepTile s = steps[blockIdx.y];
   const TileDev t = tiles[s.tile];
-  const int n = t.n;
-  const int px = blockIdx.x * 256 + threadIdx.x;
-  if (px >= n * n) return;
-  const int ky = px / n, kx = px % n;
+  if ((int)blockIdx.x >= t.nd) return;
+  const int n = t.n, nn = n * n;
+  const int kx = t.kx0 + blockIdx.x;
   const int2 ch = t.chord[kx];
-  if (ky < ch.x || ky > ch.y) return;
-  float2 acc = make_float2(0.0f, 0.0f);
-  for (int m = 0; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * n * n + px]);
-  t.P[px] = cadd(t.P[px], cscale(acc, 1.0f / (float)s.count));
+  const float inv = 1.0f / (float)s.count;
+  for (int ky = ch.x + (int)threadIdx.x; ky <= ch.y; ky += 128) {
+    const int px = ky * n + kx;
+    float2 acc = t.dP[px];
+    for (int m = 1; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * nn + px]);
+    t.P[px] = cadd(t.P[px], cscale(acc, inv));
+  }
 }
 
 // ============================================ end of an iteration (FP64)
@@ -787,8 +820,7 @@ hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, i
 hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
                                hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n * n + 255) / 256, count), dim3(256), 0, st,
-                     tiles, steps);
+  hipLaunchKernelGGL(pupil_reduce_kernel, dim3(n, count), dim3(128), 0, st, tiles, steps);
   return hipGetLastError();
 }
 
