@@ -119,6 +119,78 @@ def cpu_baseline(n_tiles: int = 8):
                       f"workload ({updates} updates, {wall:.1f} s wall)"}
 
 
+def serving_bench(fpm, n_req: int = 48, load: float = 0.8, seed: int = 5):
+    """Requests shaped like single uneven tiles (64/128 px, 9x9..21x21 LEDs,
+    5..30 iterations) arriving as a Poisson stream at `load` x the saturated
+    request rate measured closed-loop; p50/p99 latency and sustained updates/s."""
+    import numpy as np
+    import torch
+    import fpm_synth
+
+    reqs = []
+    for td in fpm_synth.uneven_batch(T=4 * n_req, workload=4, sizes=(64, 128)):
+        d = td.desc
+        for up in td.up_candidates:
+            d.upsample = up
+            try:
+                plan = fpm.Plan([d])
+                break
+            except fpm.FpmError:
+                plan = None
+        if plan is None:
+            continue
+        obj = fpm_synth.random_object(td.rng, d.N).astype(np.complex64)
+        o = torch.from_numpy(obj.reshape(-1).view(np.float32)).cuda()
+        I = torch.empty(plan.total_intensity, dtype=torch.float32, device="cuda")
+        fpm.fpm_forward(plan, o, None, I, fpm.FPM_MEM_DEVICE)
+        torch.cuda.synchronize()
+        c = td.peak_photons / float(I.max())
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed + len(reqs))
+        I = torch.poisson(I.clamp_min(0) * c, generator=gen) / c
+        reqs.append((d, I.contiguous()))
+        if len(reqs) == n_req:
+            break
+    torch.cuda.synchronize()
+    budget = int(0.5 * torch.cuda.mem_get_info()[0])
+    # closed loop: everything at once -> saturated request rate
+    srv = fpm.Server(budget, max_slots=256)
+    t0 = time.perf_counter()
+    ids = [srv.submit(d, I, fpm.FPM_MEM_DEVICE) for d, I in reqs]
+    for i, (d, _) in zip(ids, reqs):
+        srv.wait(i, d)
+    t_sat = time.perf_counter() - t0
+    srv.close()
+    rate = load * len(reqs) / t_sat
+    # open loop: Poisson arrivals at `rate`
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    srv = fpm.Server(budget, max_slots=256)
+    start = time.perf_counter()
+    due = start
+    ids = []
+    for (d, I), g in zip(reqs, gaps):
+        due += g
+        while time.perf_counter() < due:
+            time.sleep(min(1e-3, max(0.0, due - time.perf_counter())))
+        ids.append(srv.submit(d, I, fpm.FPM_MEM_DEVICE))
+    lat, first, last, upd = [], None, None, 0
+    for i, (d, _) in zip(ids, reqs):
+        _, st = srv.wait(i, d)
+        lat.append(st.finish_s - st.submit_s)
+        first = st.submit_s if first is None else min(first, st.submit_s)
+        last = st.finish_s if last is None else max(last, st.finish_s)
+        upd += st.updates
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": len(reqs), "load": load, "arrival_rate_per_s": round(rate, 2),
+            "saturated_updates_per_s": round(sum(d.L * d.iterations for d, _ in reqs) / t_sat, 1),
+            "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "sustained_updates_per_s": round(upd / (last - first), 1),
+            "mix": "64/128 px tiles, 81-441 LEDs, 5-30 iterations, FP32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +200,7 @@ def main():
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (tiles are "
@@ -178,6 +251,10 @@ def main():
     log("kernel time per kind: " + json.dumps(prof))
     roof = roofline(plan, prof)
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(fpm)
+        log("serving: " + json.dumps(serving))
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     info = plan.infos[0]
     out = {
@@ -204,6 +281,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
     }
     print(json.dumps(out), flush=True)

@@ -298,3 +298,68 @@ def split_tiles(plan: Plan, obj: np.ndarray, pup: np.ndarray, res: np.ndarray):
         r = res[i.residual_offset:i.residual_offset + i.iterations]
         out.append((o, p, r))
     return out
+
+
+# --------------------------------------------------------------- serving
+
+@dataclass
+class RequestStats:
+    submit_s: float
+    admit_s: float
+    finish_s: float
+    updates: int
+    status: int
+
+
+class Server:
+    """Owner of an ``fpm_server_t`` (continuous-batching request loop)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64):
+        h = C.c_void_p()
+        check(lib.fpm_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self._h = h
+        self._keep = {}   # request id -> (desc, buffer) kept alive until collected
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.fpm_server_destroy(self._h)
+            self._h = C.c_void_p()
+        self._keep = {}
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, desc, intensity, where: int) -> int:
+        rid = C.c_uint64()
+        cd = to_c_desc(desc)
+        check(lib.fpm_submit(self._h, C.byref(cd), _ptr(intensity, where), where, C.byref(rid)))
+        self._keep[rid.value] = (cd, intensity)
+        return rid.value
+
+    def _collect(self, fn, rid, desc, *extra):
+        N = desc.n * desc.upsample
+        obj = np.zeros((N, N), np.complex64)
+        pup = np.zeros((desc.n, desc.n), np.complex64)
+        res = np.zeros(max(desc.iterations, 1), np.float64)
+        st = RequestStatsC()
+        status = fn(self._h, rid, *extra, C.c_void_p(obj.ctypes.data), C.c_void_p(pup.ctypes.data),
+                    C.c_void_p(res.ctypes.data), C.byref(st))
+        stats = RequestStats(st.submit_s, st.admit_s, st.finish_s, st.updates, st.status)
+        if status == FPM_PENDING:
+            return None, stats
+        self._keep.pop(rid, None)
+        check(status)
+        return (obj, pup, res[:desc.iterations]), stats
+
+    def poll(self, rid: int, desc):
+        """(outputs, stats) once finished; (None, stats) while pending."""
+        return self._collect(lib.fpm_poll, rid, desc)
+
+    def wait(self, rid: int, desc, timeout_s: float = 600.0):
+        return self._collect(lib.fpm_wait, rid, desc, C.c_double(timeout_s))
+
+    def cancel(self, rid: int) -> None:
+        check(lib.fpm_cancel(self._h, rid))

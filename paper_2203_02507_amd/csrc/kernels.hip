@@ -377,14 +377,18 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
     const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+    // |psi|^2 below 2^-120 counts as zero amplitude (psi' = sqrt(I)): the
+    // hardware reciprocal square root flushes denormal inputs, and a field
+    // that small carries no phase information in single precision anyway
     const float p2 = cabs2(a[k]);
-    const float rinv = p2 > 0.0f ? __builtin_amdgcn_rsqf(p2) : 0.0f;
+    const bool live = p2 >= 0x1p-120f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(p2) : 0.0f;
     const float amp = p2 * rinv;
     const float d = amp - m;
     e_acc = fmaf(d, d, e_acc);
     i_acc += I;
     const float s = m * rinv;
-    a[k] = p2 > 0.0f ? cscale(a[k], s) : make_float2(m, 0.0f);
+    a[k] = live ? cscale(a[k], s) : make_float2(m, 0.0f);
   }
   {
     double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
@@ -497,17 +501,19 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 
 // ============================================== pupil mean of a group
 // P <- P + (1/count) sum_m dP[m] on D0, members summed in slot order.
-// Block (c, tile): support column kx0 + c; thread: a row of its chord.
+// Block (r, tile): support row ky = kx0 + r (D0 is symmetric under
+// transposition, so the column chords are also the row chords); threads run
+// along the row, so every access is contiguous.
 __global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
                                                            const StepTile* __restrict__ steps) {
   const StepTile s = steps[blockIdx.y];
   const TileDev t = tiles[s.tile];
   if ((int)blockIdx.x >= t.nd) return;
   const int n = t.n, nn = n * n;
-  const int kx = t.kx0 + blockIdx.x;
-  const int2 ch = t.chord[kx];
+  const int ky = t.kx0 + blockIdx.x;
+  const int2 ch = t.chord[ky];
   const float inv = 1.0f / (float)s.count;
-  for (int ky = ch.x + (int)threadIdx.x; ky <= ch.y; ky += 128) {
+  for (int kx = ch.x + (int)threadIdx.x; kx <= ch.y; kx += 128) {
     const int px = ky * n + kx;
     float2 acc = t.dP[px];
     for (int m = 1; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * nn + px]);

@@ -1,26 +1,548 @@
-// Serving entry points (include/fpm.h).  Placeholder until the request loop
-// lands: every call reports FPM_E_UNSUPPORTED.
+// Serving: a request loop with continuous batching.
+//
+// Requests are single-tile reconstructions (Sec. 3.1: tiles are independent
+// problems).  A host thread admits waiting requests while their device
+// footprint fits the budget and a slot is free, keeps every admitted
+// request's spectrum and pupil resident, and on each tick launches the next
+// dependent step (one LED, or one LED group, Sec. 3.2) of every admitted
+// request in the same kernels.  Each request's arithmetic is independent of
+// what it is batched with (one workgroup per update, per-tile reductions in
+// fixed order), so a result is bitwise the same alone and in a mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "fpm_internal.h"
 #include "runtime.h"
 
 using namespace fpm;
 
+namespace {
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Request {
+  uint64_t id = 0;
+  TilePlan plan;
+  const float* I_user = nullptr;
+  fpm_mem where = FPM_MEM_HOST;
+  fpm_status status = FPM_PENDING;
+  bool cancelled = false;
+  fpm_request_stats stats{};
+  // device state (one allocation) and the request's table slot
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  TileDev td{};
+  int slot = -1;
+  float2* obj_stage = nullptr;
+  float* I_copy = nullptr;
+  // progress
+  int iter = 0, step = 0;
+  // results (host)
+  std::vector<float2> obj, pupil;
+  std::vector<double> residual;
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t footprint(const TilePlan& tp, fpm_mem where) {
+  const size_t nn = (size_t)tp.n * tp.n, NN = (size_t)tp.N * tp.N;
+  const bool grouped = tp.d.schedule == FPM_SCHED_LED_GROUPS && tp.d.pupil_update;
+  size_t b = 0;
+  b += align256(NN * 8);                                  // S
+  b += align256(nn * 8);                                  // P
+  b += align256((grouped ? tp.max_group : 1) * nn * 8);   // dP
+  b += 2 * align256((size_t)tp.L * 8);                    // e, i partials
+  b += 2 * align256(8);                                   // sigma, smax
+  b += align256((size_t)tp.n * 8);                        // chord
+  b += align256(nn * 8);                                  // P0
+  b += align256((size_t)std::max(1, tp.d.iterations) * 8);
+  b += align256(NN * 8);                                  // object stage
+  if (where == FPM_MEM_HOST) b += align256((size_t)tp.L * nn * 4);
+  b += align256(4 * sizeof(LineJob));
+  return b;
+}
+
+}  // namespace
+
+struct fpm_server_s {
+  size_t budget = 0, used = 0;
+  int max_slots = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> waiting;
+  std::vector<Request*> active;
+  std::map<uint64_t, std::unique_ptr<Request>> all;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  // device tables rebuilt per tick
+  DevBuf table, items, steps, ids, jobs;
+  std::vector<int> free_slots;
+  std::vector<TileDev> host_table;
+  fpm_status fatal = FPM_OK;
+
+  void run();
+  bool admit(Request* r, std::string& err);
+  void release(Request* r);
+  hipError_t tick(std::vector<Request*>& batch);
+  hipError_t finish(Request* r);
+};
+
+bool fpm_server_s::admit(Request* r, std::string& err) {
+  const TilePlan& tp = r->plan;
+  const size_t nn = (size_t)tp.n * tp.n, NN = (size_t)tp.N * tp.N;
+  r->dev_bytes = footprint(tp, r->where);
+  if (hipMalloc(&r->dev, r->dev_bytes) != hipSuccess) {
+    err = "hipMalloc failed";
+    return false;
+  }
+  char* p = (char*)r->dev;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += align256(bytes);
+    return q;
+  };
+  const bool grouped = tp.d.schedule == FPM_SCHED_LED_GROUPS && tp.d.pupil_update;
+  TileDev& d = r->td;
+  d.S = (float2*)take(NN * 8);
+  d.P = (float2*)take(nn * 8);
+  d.dP = (float2*)take((grouped ? tp.max_group : 1) * nn * 8);
+  d.e_part = (double*)take((size_t)tp.L * 8);
+  d.i_part = (double*)take((size_t)tp.L * 8);
+  d.sigma = (double*)take(8);
+  d.smax = (unsigned*)take(8);
+  d.chord = (const int2*)take((size_t)tp.n * 8);
+  d.P0 = (const float2*)take(nn * 8);
+  d.residual = (double*)take((size_t)std::max(1, tp.d.iterations) * 8);
+  r->obj_stage = (float2*)take(NN * 8);
+  if (r->where == FPM_MEM_HOST) r->I_copy = (float*)take((size_t)tp.L * nn * 4);
+  LineJob* jobs_dev = (LineJob*)take(4 * sizeof(LineJob));
+  d.I = r->where == FPM_MEM_HOST ? r->I_copy : r->I_user;
+  d.N = tp.N;
+  d.L = tp.L;
+  d.n = tp.n;
+  d.kx0 = tp.kx0;
+  d.nd = tp.nd;
+  d.nd0 = tp.nd0;
+  d.up = tp.d.upsample;
+  d.j0 = tp.step_leds.empty() ? 0 : tp.step_leds[0];
+  d.wy0_j0 = tp.N / 2 - tp.n / 2;
+  d.wx0_j0 = tp.N / 2 - tp.n / 2;
+  d.mode = !tp.d.pupil_update ? 0 : (grouped ? 2 : 1);
+  d.iters = tp.d.iterations;
+  hipError_t e = hipSuccess;
+  if (r->where == FPM_MEM_HOST)
+    e = hipMemcpyAsync(r->I_copy, r->I_user, (size_t)tp.L * nn * 4, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)d.chord, tp.chord.data(), (size_t)tp.n * 8, hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)d.P0, tp.pupil0.data(), nn * 8, hipMemcpyHostToDevice, stream);
+  // line-FFT jobs: initial window rows/cols (forward), object rows/cols (inverse)
+  LineJob hj[4];
+  for (int pass = 0; pass < 2; ++pass) {
+    LineJob& j = hj[pass];
+    j = LineJob{};
+    j.base = d.S + (size_t)d.wy0_j0 * d.N + d.wx0_j0;
+    j.line_stride = pass == 0 ? d.N : 1;
+    j.elem_stride = pass == 0 ? 1 : d.N;
+    j.nlines = d.n;
+    j.scale = 1.0f;
+    LineJob& f = hj[2 + pass];
+    f = LineJob{};
+    f.base = r->obj_stage;
+    f.line_stride = pass == 0 ? d.N : 1;
+    f.elem_stride = pass == 0 ? 1 : d.N;
+    f.nlines = d.N;
+    f.scale = 1.0f;
+    f.modulate = pass == 1;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(jobs_dev, hj, sizeof hj, hipMemcpyHostToDevice, stream);
+  // table slot
+  r->slot = free_slots.back();
+  free_slots.pop_back();
+  host_table[r->slot] = d;
+  TileDev* tab = (TileDev*)table.p;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tab + r->slot, &host_table[r->slot], sizeof(TileDev), hipMemcpyHostToDevice,
+                       stream);
+  // initial state
+  int* ids_d = (int*)ids.p;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ids_d, &r->slot, sizeof(int), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = launch_init_state(tab, ids_d, 1, d.n, d.N, stream);
+  if (e == hipSuccess) e = launch_line_fft(jobs_dev, 1, d.n, d.n, 0, stream);
+  if (e == hipSuccess) e = launch_line_fft(jobs_dev + 1, 1, d.n, d.n, 0, stream);
+  if (e == hipSuccess) e = launch_smax(tab, ids_d, 1, d.N * d.N, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  r->stats.admit_s = now_s(t0);
+  used += r->dev_bytes;
+  if (e != hipSuccess) {
+    err = std::string("admission: ") + hipGetErrorString(e);
+    return false;
+  }
+  return true;
+}
+
+void fpm_server_s::release(Request* r) {
+  if (r->dev) {
+    (void)hipFree(r->dev);
+    used -= r->dev_bytes;
+    r->dev = nullptr;
+  }
+  if (r->slot >= 0) {
+    free_slots.push_back(r->slot);
+    r->slot = -1;
+  }
+}
+
+hipError_t fpm_server_s::finish(Request* r) {
+  // object = up^2 IFFT_N(shift(sigma S)): scale into the stage, two passes of line IFFTs
+  const TilePlan& tp = r->plan;
+  const size_t NN = (size_t)tp.N * tp.N, nn = (size_t)tp.n * tp.n;
+  TileDev* tab = (TileDev*)table.p;
+  const LineJob* jobs_dev = (const LineJob*)((char*)r->obj_stage + align256(NN * 8) +
+                                             (r->where == FPM_MEM_HOST
+                                                  ? align256((size_t)tp.L * nn * 4)
+                                                  : 0));
+  int64_t zero = 0;
+  hipError_t e = hipMemcpyAsync(ids.p, &zero, sizeof zero, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = launch_scale_spectrum(tab + r->slot, 1, r->obj_stage, (const int64_t*)ids.p, tp.N, stream);
+  if (e == hipSuccess) e = launch_line_fft(jobs_dev + 2, 1, tp.N, tp.N, 1, stream);
+  if (e == hipSuccess) e = launch_line_fft(jobs_dev + 3, 1, tp.N, tp.N, 1, stream);
+  r->obj.resize(NN);
+  r->pupil.resize(nn);
+  r->residual.resize(std::max(1, tp.d.iterations));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(r->obj.data(), r->obj_stage, NN * 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(r->pupil.data(), r->td.P, nn * 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(r->residual.data(), r->td.residual, r->residual.size() * 8,
+                       hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+// One scheduler tick: the next dependent step of every admitted request.
+hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
+  std::map<int, std::vector<Item>> by_n;
+  std::map<int, int> nd_max;
+  std::vector<StepTile> st;
+  std::vector<int> ends;
+  int n_max = 0;
+  for (Request* r : batch) {
+    const TilePlan& tp = r->plan;
+    const int s = r->step;
+    for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
+      const int j = tp.step_leds[m];
+      Item it{};
+      it.tile = r->slot;
+      it.led = j;
+      it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+      it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+      it.slot = m - tp.step_beg[s];
+      by_n[tp.n].push_back(it);
+    }
+    nd_max[tp.n] = std::max(nd_max[tp.n], tp.nd);
+    n_max = std::max(n_max, tp.n);
+    if (r->td.mode == 2) st.push_back(StepTile{r->slot, tp.step_beg[s + 1] - tp.step_beg[s]});
+    if (s + 1 == tp.nsteps) ends.push_back(r->slot);
+  }
+  size_t nitems = 0;
+  for (auto& kv : by_n) nitems += kv.second.size();
+  hipError_t e = items.alloc(std::max<size_t>(1, nitems) * sizeof(Item));
+  if (e == hipSuccess) e = steps.alloc(std::max<size_t>(1, st.size()) * sizeof(StepTile));
+  if (e != hipSuccess) return e;
+  std::vector<Item> flat;
+  flat.reserve(nitems);
+  std::vector<std::pair<int, size_t>> ranges;
+  for (auto& kv : by_n) {
+    ranges.emplace_back(kv.first, flat.size());
+    flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+  }
+  e = hipMemcpyAsync(items.p, flat.data(), flat.size() * sizeof(Item), hipMemcpyHostToDevice,
+                     stream);
+  if (e == hipSuccess && !st.empty())
+    e = hipMemcpyAsync(steps.p, st.data(), st.size() * sizeof(StepTile), hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess && !ends.empty())
+    e = hipMemcpyAsync(ids.p, ends.data(), ends.size() * sizeof(int), hipMemcpyHostToDevice,
+                       stream);
+  const TileDev* tab = (const TileDev*)table.p;
+  for (size_t i = 0; e == hipSuccess && i < ranges.size(); ++i) {
+    const size_t b = ranges[i].second;
+    const size_t cnt = (i + 1 < ranges.size() ? ranges[i + 1].second : flat.size()) - b;
+    e = launch_update(ranges[i].first, tab, (const Item*)items.p + b, (int)cnt,
+                      nd_max[ranges[i].first], stream);
+  }
+  if (e == hipSuccess && !st.empty())
+    e = launch_pupil_reduce(tab, (const StepTile*)steps.p, (int)st.size(), n_max, stream);
+  // iteration ends: residual + normalisation; spectrum max for the next iteration
+  if (e == hipSuccess && !ends.empty()) {
+    // every request ending an iteration in this tick is at its own iteration index;
+    // launch per distinct index (usually one)
+    std::map<int, std::vector<int>> by_iter;
+    for (Request* r : batch)
+      if (r->step + 1 == r->plan.nsteps) by_iter[r->iter].push_back(r->slot);
+    size_t off = 0;
+    std::vector<int> flat_ids;
+    for (auto& kv : by_iter) flat_ids.insert(flat_ids.end(), kv.second.begin(), kv.second.end());
+    e = hipMemcpyAsync(ids.p, flat_ids.data(), flat_ids.size() * sizeof(int),
+                       hipMemcpyHostToDevice, stream);
+    for (auto& kv : by_iter) {
+      if (e != hipSuccess) break;
+      e = launch_iter_end(tab, (const int*)ids.p + off, (int)kv.second.size(), kv.first, stream);
+      if (e == hipSuccess) {
+        int nmax = 0;
+        for (Request* r : batch)
+          if (r->step + 1 == r->plan.nsteps) nmax = std::max(nmax, r->plan.N);
+        e = launch_smax(tab, (const int*)ids.p + off, (int)kv.second.size(), nmax * nmax, stream);
+      }
+      off += kv.second.size();
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+void fpm_server_s::run() {
+  (void)hipSetDevice(device);
+  while (true) {
+    std::vector<Request*> batch;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !waiting.empty() || !active.empty(); });
+      if (stop) break;
+      // drop cancelled requests
+      for (auto it = active.begin(); it != active.end();) {
+        if ((*it)->cancelled) {
+          release(*it);
+          (*it)->status = FPM_E_CANCELLED;
+          (*it)->stats.finish_s = now_s(t0);
+          it = active.erase(it);
+          cv_done.notify_all();
+        } else {
+          ++it;
+        }
+      }
+      // admission by device footprint and free slots (first come, first served)
+      while (!waiting.empty() && (int)active.size() < max_slots) {
+        Request* r = waiting.front();
+        if (r->cancelled) {
+          waiting.pop_front();
+          r->status = FPM_E_CANCELLED;
+          r->stats.finish_s = now_s(t0);
+          cv_done.notify_all();
+          continue;
+        }
+        if (used + footprint(r->plan, r->where) > budget) break;
+        waiting.pop_front();
+        std::string err;
+        if (!admit(r, err)) {
+          release(r);
+          r->status = FPM_E_DEVICE;
+          g_last_error = err;
+          cv_done.notify_all();
+          continue;
+        }
+        if (r->plan.d.iterations == 0) {
+          const hipError_t e = finish(r);
+          release(r);
+          r->status = e == hipSuccess ? FPM_OK : FPM_E_DEVICE;
+          r->stats.finish_s = now_s(t0);
+          cv_done.notify_all();
+          continue;
+        }
+        active.push_back(r);
+      }
+      batch = active;
+    }
+    if (batch.empty()) continue;
+    const hipError_t e = tick(batch);
+    std::lock_guard<std::mutex> lk(mu);
+    if (e != hipSuccess) {
+      for (Request* r : batch) {
+        release(r);
+        r->status = FPM_E_DEVICE;
+      }
+      active.clear();
+      fatal = FPM_E_DEVICE;
+      g_last_error = std::string("server tick: ") + hipGetErrorString(e);
+      cv_done.notify_all();
+      continue;
+    }
+    for (auto it = active.begin(); it != active.end();) {
+      Request* r = *it;
+      r->stats.updates += r->plan.step_beg[r->step + 1] - r->plan.step_beg[r->step];
+      bool done = false;
+      if (++r->step == r->plan.nsteps) {
+        r->step = 0;
+        if (++r->iter == r->plan.d.iterations) done = true;
+      }
+      if (done) {
+        const hipError_t fe = finish(r);
+        bool finite = true;
+        for (double v : r->residual) finite &= std::isfinite(v);
+        release(r);
+        r->status = fe != hipSuccess ? FPM_E_DEVICE : (finite ? FPM_OK : FPM_E_DIVERGED);
+        r->stats.finish_s = now_s(t0);
+        it = active.erase(it);
+        cv_done.notify_all();
+      } else {
+        ++it;
+      }
+    }
+  }
+}
+
 extern "C" {
-fpm_status fpm_server_create(size_t, int32_t, fpm_server_t** out) {
-  if (out) *out = nullptr;
-  return fail(FPM_E_UNSUPPORTED, "serving is not built yet");
+
+fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t** out) {
+  if (!out || max_slots < 1 || max_slots > 65536 || hbm_budget_bytes == 0)
+    return fail(FPM_E_ARG, "fpm_server_create: bad argument");
+  *out = nullptr;
+  std::unique_ptr<fpm_server_s> s(new (std::nothrow) fpm_server_s());
+  if (!s) return fail(FPM_E_NOMEM, "fpm_server_create: host allocation failed");
+  s->budget = hbm_budget_bytes;
+  s->max_slots = max_slots;
+  s->t0 = std::chrono::steady_clock::now();
+  fpm_status st = FPM_OK;
+  if (!hip_ok(hipGetDevice(&s->device), "hipGetDevice", &st) ||
+      !hip_ok(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate", &st) ||
+      !hip_ok(s->table.alloc(sizeof(TileDev) * max_slots), "hipMalloc(table)", &st) ||
+      !hip_ok(s->ids.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st))
+    return st;
+  s->host_table.assign(max_slots, TileDev{});
+  for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  fpm_server_s* raw = s.release();
+  raw->worker = std::thread([raw] { raw->run(); });
+  *out = raw;
+  return FPM_OK;
 }
-void fpm_server_destroy(fpm_server_t*) {}
-fpm_status fpm_submit(fpm_server_t*, const fpm_tile_desc*, const float*, fpm_mem, uint64_t*) {
-  return fail(FPM_E_UNSUPPORTED, "serving is not built yet");
+
+void fpm_server_destroy(fpm_server_t* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->all) s->release(kv.second.get());
+  (void)hipStreamDestroy(s->stream);
+  delete s;
 }
-fpm_status fpm_poll(fpm_server_t*, uint64_t, void*, void*, double*, fpm_request_stats*) {
-  return fail(FPM_E_UNSUPPORTED, "serving is not built yet");
+
+fpm_status fpm_submit(fpm_server_t* s, const fpm_tile_desc* tile, const float* intensity,
+                      fpm_mem where, uint64_t* id) {
+  if (!s || !tile || !intensity || !id || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_submit: bad argument");
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) return fail(FPM_E_NOMEM, "fpm_submit: host allocation failed");
+  std::string err;
+  const fpm_status ps = build_tile_plan(*tile, r->plan, err);
+  if (ps != FPM_OK) return fail(ps, "fpm_submit: " + err);
+  if (where == FPM_MEM_HOST) {
+    const size_t cnt = (size_t)r->plan.L * r->plan.n * r->plan.n;
+    for (size_t i = 0; i < cnt; ++i)
+      if (!(intensity[i] >= 0.0f) || !std::isfinite(intensity[i]))
+        return fail(FPM_E_ARG, "fpm_submit: intensity " + std::to_string(i) +
+                                   " is negative or not finite");
+  }
+  if (footprint(r->plan, where) > s->budget)
+    return fail(FPM_E_NOMEM, "fpm_submit: request footprint exceeds the server budget");
+  r->I_user = intensity;
+  r->where = where;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->fatal != FPM_OK) return fail(s->fatal, "fpm_submit: server stopped after a device error");
+  r->id = s->next_id++;
+  r->stats.submit_s = now_s(s->t0);
+  r->stats.status = FPM_PENDING;
+  *id = r->id;
+  s->waiting.push_back(r.get());
+  s->all[r->id] = std::move(r);
+  s->cv_work.notify_all();
+  return FPM_OK;
 }
-fpm_status fpm_wait(fpm_server_t*, uint64_t, double, void*, void*, double*, fpm_request_stats*) {
-  return fail(FPM_E_UNSUPPORTED, "serving is not built yet");
+
+static fpm_status collect(fpm_server_t* s, std::unique_lock<std::mutex>& lk, uint64_t id,
+                          void* object_out, void* pupil_out, double* residual_out,
+                          fpm_request_stats* stats) {
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(FPM_E_ARG, "fpm_poll: unknown request id");
+  Request* r = it->second.get();
+  if (r->status == FPM_PENDING) {
+    if (stats) {
+      *stats = r->stats;
+      stats->status = FPM_PENDING;
+    }
+    return FPM_PENDING;
+  }
+  const fpm_status st = r->status;
+  if (st == FPM_OK) {
+    if (object_out) std::memcpy(object_out, r->obj.data(), r->obj.size() * 8);
+    if (pupil_out) std::memcpy(pupil_out, r->pupil.data(), r->pupil.size() * 8);
+    if (residual_out)
+      std::memcpy(residual_out, r->residual.data(), (size_t)r->plan.d.iterations * 8);
+  }
+  if (stats) {
+    *stats = r->stats;
+    stats->status = st;
+  }
+  s->all.erase(it);
+  (void)lk;
+  if (st != FPM_OK)
+    return fail(st, st == FPM_E_CANCELLED ? "request cancelled" : "request failed");
+  return FPM_OK;
 }
-fpm_status fpm_cancel(fpm_server_t*, uint64_t) {
-  return fail(FPM_E_UNSUPPORTED, "serving is not built yet");
+
+fpm_status fpm_poll(fpm_server_t* s, uint64_t id, void* object_out, void* pupil_out,
+                    double* residual_out, fpm_request_stats* stats) {
+  if (!s) return fail(FPM_E_ARG, "fpm_poll: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  return collect(s, lk, id, object_out, pupil_out, residual_out, stats);
 }
+
+fpm_status fpm_wait(fpm_server_t* s, uint64_t id, double timeout_s, void* object_out,
+                    void* pupil_out, double* residual_out, fpm_request_stats* stats) {
+  if (!s) return fail(FPM_E_ARG, "fpm_wait: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  const auto deadline = std::chrono::steady_clock::now() +
+                        std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                            std::chrono::duration<double>(std::max(0.0, timeout_s)));
+  s->cv_done.wait_until(lk, deadline, [&] {
+    auto it = s->all.find(id);
+    return it == s->all.end() || it->second->status != FPM_PENDING;
+  });
+  return collect(s, lk, id, object_out, pupil_out, residual_out, stats);
 }
+
+fpm_status fpm_cancel(fpm_server_t* s, uint64_t id) {
+  if (!s) return fail(FPM_E_ARG, "fpm_cancel: NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(FPM_E_ARG, "fpm_cancel: unknown request id");
+  it->second->cancelled = true;
+  s->cv_work.notify_all();
+  return FPM_OK;
+}
+
+}  // extern "C"

@@ -173,3 +173,19 @@ def test_mixed_sizes_and_edge_cases(fpm, orc):
         else:
             assert rel(o, o_ref) <= TOL_OBJ, t
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
+
+
+def test_large_board_far_leds_match_oracle(fpm, orc):
+    """21x21 LEDs: the outermost windows are nearly empty at first, so |psi|
+    reaches the bottom of the single-precision range; results must stay
+    finite and match the oracle."""
+    d = fpm_synth.TileDesc(n=64, upsample=4, led_rows=21, led_cols=21, iterations=2,
+                           schedule=1, pupil_update=1, defocus_um=-7.6)
+    td = fpm_synth.TileDraw(desc=d, rng=np.random.default_rng(3))
+    _, _, I = orc.synthesize(td)
+    _, out = run_gpu(fpm, [d], [I])
+    o, P, r = out[0]
+    assert np.all(np.isfinite(o)) and np.all(np.isfinite(r))
+    o_ref, P_ref, r_ref = oracle_run(orc, d, I)
+    assert rel(o, o_ref) <= TOL_OBJ
+    assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)

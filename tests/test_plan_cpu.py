@@ -121,3 +121,14 @@ def test_host_mode_rejects_bad_intensities_without_gpu_work(fpm):
     I[3, 2, 1] = np.nan
     with pytest.raises(fpm.FpmError):
         fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_HOST)
+
+
+def test_server_without_gpu_fails_cleanly(fpm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("covered by the GPU tests")
+    with pytest.raises(fpm.FpmError):
+        fpm.Server(1 << 30, 4)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Server(0, 4)
+    assert e.value.status == fpm.FPM_E_ARG
