@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (tiles are "
@@ -246,6 +248,13 @@ def main():
     if not all(math.isfinite(x) for x in r):
         raise SystemExit("non-finite residual")
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=device).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prof = fpm.fpm_profile_reconstruct(plan, I)
     torch.cuda.synchronize()
     log("kernel time per kind: " + json.dumps(prof))

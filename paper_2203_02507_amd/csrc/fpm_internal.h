@@ -68,8 +68,11 @@ struct StepTile {  // a tile that ran a group in this step
 
 // Kernel launchers (kernels.hip).  All enqueue on `st` and return the HIP
 // status of the launch.
+// `variant` selects the LDS row padding of the transpose buffer
+// (0: 16, 1: 1, 2: 8, 3: 32 complex elements); results are identical.
+constexpr int kUpdateVariants = 4;
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         hipStream_t st);
+                         int variant, hipStream_t st);
 hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
                                float* out, const int64_t* out_off, int nd_max, hipStream_t st);
 hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,

@@ -112,9 +112,49 @@ constexpr int bitrev(int v, int bits) {
   return r;
 }
 
-// R-point FFT on registers, natural order in and out (R a power of two).
+template <int R, bool INV>
+__device__ __forceinline__ void fft_reg_pow2(float2 (&a)[R]);
+
+// R-point FFT on registers, natural order in and out.  R = 2^k, or 3 * 2^k
+// (one radix-3 decimation-in-time step over three power-of-two sub-FFTs:
+// X[k + M s] = sum_r W_R^{r k} Y_r[k] W_3^{r s}, Y_r the M-point FFT of
+// x[3 m + r]).
 template <int R, bool INV>
 __device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
+  if constexpr (R % 3 == 0) {
+    constexpr int M = R / 3;
+    float2 y0[M], y1[M], y2[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      y0[m] = a[3 * m];
+      y1[m] = a[3 * m + 1];
+      y2[m] = a[3 * m + 2];
+    }
+    fft_reg_pow2<M, INV>(y0);
+    fft_reg_pow2<M, INV>(y1);
+    fft_reg_pow2<M, INV>(y2);
+    // W_3 = exp(-+2 pi i / 3): -1/2 -+ i sqrt(3)/2
+    const float s3 = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
+#pragma unroll
+    for (int kk = 0; kk < M; ++kk) {
+      const float2 t0 = y0[kk];
+      const float2 t1 = tw_mul<R, INV>(y1[kk], kk, R);
+      const float2 t2 = tw_mul<R, INV>(y2[kk], 2 * kk, R);
+      const float2 sum = cadd(t1, t2), dif = csub(t1, t2);
+      const float2 mid = make_float2(t0.x - 0.5f * sum.x, t0.y - 0.5f * sum.y);
+      const float2 rot = make_float2(-s3 * dif.y, s3 * dif.x);  // i * s3 * dif
+      a[kk] = cadd(t0, sum);
+      a[kk + M] = cadd(mid, rot);
+      a[kk + 2 * M] = csub(mid, rot);
+    }
+  } else {
+    fft_reg_pow2<R, INV>(a);
+  }
+}
+
+// R-point FFT on registers, natural order in and out (R a power of two).
+template <int R, bool INV>
+__device__ __forceinline__ void fft_reg_pow2(float2 (&a)[R]) {
   constexpr int LB = ilog2(R);
   float2 b[R];
 #pragma unroll
@@ -246,9 +286,11 @@ __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, float
   __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
 }
 
-template <int n>
+// complex elements per row of the LDS transpose buffer; the padding only
+// moves rows across LDS banks (the autotuner picks it per tile size)
+template <int n, int PAD = 16>
 constexpr int pitch() {
-  return n + 16;  // complex elements per LDS row (padding against bank conflicts)
+  return n + PAD;
 }
 
 template <typename T>
@@ -287,14 +329,14 @@ __device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_
 }
 
 // phase B input: lane q of row y takes kx = q + 4p from T[kx - kx0][y]
-template <int n>
+template <int n, int PAD = 16>
 __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, int y, int q,
                                           float2 (&a)[n / kQ]) {
   constexpr int R = n / kQ;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
     const int c = q + kQ * p - kx0;
-    a[p] = (c >= 0 && c < nd) ? buf[c * pitch<n>() + y] : make_float2(0.0f, 0.0f);
+    a[p] = (c >= 0 && c < nd) ? buf[c * pitch<n, PAD>() + y] : make_float2(0.0f, 0.0f);
   }
 }
 
@@ -303,7 +345,7 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
 // ===================================================== the update kernel
 // t.mode: 0 = spectrum only, 1 = pupil updated in place (one LED per tile in
 // the launch), 2 = pupil increment written to dP[slot] (LED groups).
-template <int n>
+template <int n, int PAD>
 __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restrict__ tiles,
                                                         const Item* __restrict__ items) {
   constexpr int R = n / kQ;
@@ -358,7 +400,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   if (col_line) {
     pm = gather_phi<n>(Sw, Pw, N, kx, ch, q, sigf / (float)(n * n), a);
     line_dit<n, true>(a, q, tw);
-    float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
+    float2* dst = sbuf + line * pitch<n, PAD>() + R * brev2(q);
 #pragma unroll
     for (int k = 0; k < R; ++k) dst[k] = a[k];
   }
@@ -367,7 +409,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   lds_barrier();
 
   // ---- phase B: rows, IFFT along kx
-  load_rows<n>(sbuf, t.kx0, t.nd, line, q, a);
+  load_rows<n, PAD>(sbuf, t.kx0, t.nd, line, q, a);
   lds_barrier();  // T fully consumed; the buffer is reused below
   line_dit<n, true>(a, q, tw);
 
@@ -377,18 +419,25 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
     const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
-    // |psi|^2 below 2^-120 counts as zero amplitude (psi' = sqrt(I)): the
-    // hardware reciprocal square root flushes denormal inputs, and a field
-    // that small carries no phase information in single precision anyway
+    // psi' = m psi / |psi| through the hardware reciprocal square root, which
+    // flushes denormal inputs: a field whose |psi|^2 is below 2^-100 is
+    // first scaled by 2^100 (exact), so every nonzero psi keeps its phase.
+    // Where psi = 0 the method sets psi' = sqrt(I) in the centred frame; this
+    // frame differs from it by (-1)^(x+y), so the zero-field value is
+    // (-1)^(x+y) sqrt(I) here.
+    const float m_zero = ((line + xc + k) & 1) ? -m : m;
     const float p2 = cabs2(a[k]);
-    const bool live = p2 >= 0x1p-120f;
-    const float rinv = live ? __builtin_amdgcn_rsqf(p2) : 0.0f;
-    const float amp = p2 * rinv;
+    const bool small = p2 < 0x1p-100f;
+    const float2 as = small ? cscale(a[k], 0x1p100f) : a[k];
+    const float p2s = small ? cabs2(as) : p2;
+    const bool live = p2s > 0.0f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(p2s) : 0.0f;
+    const float amp = p2s * rinv * (small ? 0x1p-100f : 1.0f);
     const float d = amp - m;
     e_acc = fmaf(d, d, e_acc);
     i_acc += I;
     const float s = m * rinv;
-    a[k] = live ? cscale(a[k], s) : make_float2(m, 0.0f);
+    a[k] = live ? cscale(as, s) : make_float2(m_zero, 0.0f);
   }
   {
     double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
@@ -404,13 +453,13 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int c = q + kQ * k - t.kx0;
-    if (c >= 0 && c < t.nd) sbuf[c * pitch<n>() + line] = a[k];
+    if (c >= 0 && c < t.nd) sbuf[c * pitch<n, PAD>() + line] = a[k];
   }
   lds_barrier();
 
   // ---- phase A': support columns, FFT along y, then the update
   if (col_line) {
-    const float2* srcp = sbuf + line * pitch<n>() + R * brev2(q);
+    const float2* srcp = sbuf + line * pitch<n, PAD>() + R * brev2(q);
 #pragma unroll
     for (int m = 0; m < R; ++m) a[m] = srcp[m];
     line_dif<n, false>(a, q, tw);
@@ -769,16 +818,27 @@ __global__ void set_intensity_kernel(TileDev* __restrict__ table, int count,
 
 // ========================================================== launchers
 namespace {
-template <int n>
+template <int n, int PAD = 16>
 size_t update_lds(int nd_max) {
-  return (size_t)nd_max * pitch<n>() * sizeof(float2);
+  return (size_t)nd_max * pitch<n, PAD>() * sizeof(float2);
+}
+template <int n, int PAD>
+hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, int nd_max,
+                            hipStream_t st) {
+  const size_t lds = update_lds<n, PAD>(nd_max);
+  hipLaunchKernelGGL((update_kernel<n, PAD>), dim3(count), dim3(n * kQ), lds, st, tiles, items);
+  return hipGetLastError();
 }
 template <int n>
 hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
-                           hipStream_t st) {
-  const size_t lds = update_lds<n>(nd_max);
-  hipLaunchKernelGGL(update_kernel<n>, dim3(count), dim3(n * kQ), lds, st, tiles, items);
-  return hipGetLastError();
+                           int variant, hipStream_t st) {
+  switch (variant) {
+    case 0: return launch_update_np<n, 16>(tiles, items, count, nd_max, st);
+    case 1: return launch_update_np<n, 1>(tiles, items, count, nd_max, st);
+    case 2: return launch_update_np<n, 8>(tiles, items, count, nd_max, st);
+    case 3: return launch_update_np<n, 32>(tiles, items, count, nd_max, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 template <int n>
 hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, float* out,
@@ -788,26 +848,39 @@ hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, 
                      off);
   return hipGetLastError();
 }
+template <int n>
+void set_lds_limit_n(int big) {
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)forward_kernel<n>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
 bool g_attr_done = false;
 void set_lds_limits() {
   if (g_attr_done) return;
   g_attr_done = true;
   const int big = 160 * 1024 - 4096;
-  (void)hipFuncSetAttribute((const void*)update_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)forward_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)forward_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  set_lds_limit_n<64>(big);
+  set_lds_limit_n<96>(big);
+  set_lds_limit_n<128>(big);
   (void)hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         hipStream_t st) {
+                         int variant, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   set_lds_limits();
   switch (n) {
-    case 64: return launch_update_n<64>(tiles, items, count, nd_max, st);
-    case 128: return launch_update_n<128>(tiles, items, count, nd_max, st);
+    case 64: return launch_update_n<64>(tiles, items, count, nd_max, variant, st);
+    case 96: return launch_update_n<96>(tiles, items, count, nd_max, variant, st);
+    case 128: return launch_update_n<128>(tiles, items, count, nd_max, variant, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -818,6 +891,7 @@ hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, i
   set_lds_limits();
   switch (n) {
     case 64: return launch_forward_n<64>(tiles, items, count, out, out_off, nd_max, st);
+    case 96: return launch_forward_n<96>(tiles, items, count, out, out_off, nd_max, st);
     case 128: return launch_forward_n<128>(tiles, items, count, out, out_off, nd_max, st);
     default: return hipErrorInvalidValue;
   }

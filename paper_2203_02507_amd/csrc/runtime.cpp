@@ -29,6 +29,31 @@ bool hip_ok(hipError_t e, const char* what, fpm_status* st) {
   return false;
 }
 
+// ------------------------------------------------------ variant cache
+namespace {
+std::mutex g_variant_mu;
+std::map<int, int> g_variant;
+}  // namespace
+
+int update_variant(int n) {
+  if (const char* v = std::getenv("FPM_UPDATE_VARIANT")) {
+    const int k = std::atoi(v);
+    if (k >= 0 && k < kUpdateVariants) return k;
+  }
+  std::lock_guard<std::mutex> lk(g_variant_mu);
+  auto it = g_variant.find(n);
+  return it == g_variant.end() ? 0 : it->second;
+}
+void set_update_variant(int n, int v) {
+  std::lock_guard<std::mutex> lk(g_variant_mu);
+  g_variant[n] = v;
+}
+bool update_variant_known(int n) {
+  if (std::getenv("FPM_UPDATE_VARIANT")) return true;
+  std::lock_guard<std::mutex> lk(g_variant_mu);
+  return g_variant.count(n) != 0;
+}
+
 // ------------------------------------------------------------- DevBuf
 DevBuf::~DevBuf() {
   if (p) hipFree(p);
@@ -136,8 +161,6 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     max_steps = std::max(max_steps, tp.nsteps);
     nclass[tp.n] = std::max(nclass[tp.n], tp.nd);
   }
-  for (auto& kv : nclass)
-    if (kv.first == 96) return fail(FPM_E_UNSUPPORTED, "n = 96 kernels are not built yet");
   int maxN = 0;
   for (const TilePlan& tp : tiles) maxN = std::max(maxN, tp.N);
   NN_max = maxN * maxN;
@@ -454,7 +477,7 @@ hipError_t Executor::enqueue_sweep(hipStream_t s) {
         break;
       }
       case Launch::UPDATE:
-        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, s);
+        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, update_variant(l.n), s);
         break;
       case Launch::REDUCE:
         e = launch_pupil_reduce(tab, stp + l.off, l.count, l.n, s);
@@ -471,7 +494,52 @@ hipError_t Executor::enqueue_sweep(hipStream_t s) {
   return e;
 }
 
+hipError_t Executor::tune(hipStream_t s) {
+  const TileDev* tab = (const TileDev*)table.p;
+  const Item* it = (const Item*)items_d.p;
+  std::map<int, const Launch*> biggest;
+  for (const Launch& l : launches)
+    if (l.kind == Launch::UPDATE && (!biggest.count(l.n) || biggest[l.n]->count < l.count))
+      biggest[l.n] = &l;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  tune_ms.clear();
+  for (auto& kv : biggest) {
+    if (e != hipSuccess) break;
+    if (update_variant_known(kv.first)) continue;
+    const Launch& l = *kv.second;
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < kUpdateVariants && e == hipSuccess; ++v) {
+      e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r)
+        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      tune_ms.push_back(ms / 3.0f);
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    if (e == hipSuccess) set_update_variant(kv.first, best);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
+}
+
 hipError_t Executor::run(hipStream_t s, bool use_graph) {
+  if (!tuned) {
+    // the tuning launches only scribble on state that the sweep initialises
+    const hipError_t te = tune(s);
+    if (te != hipSuccess) return te;
+    tuned = true;
+  }
   if (!use_graph) return enqueue_sweep(s);
   if (!graph_exec) {
     hipError_t e;

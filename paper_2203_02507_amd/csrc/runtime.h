@@ -29,6 +29,12 @@ struct Launch {
   int iter = 0;            // ITER_END
 };
 
+// Process-wide choice of update-kernel variant per tile size (autotuned on
+// first use; FPM_UPDATE_VARIANT=k forces one).
+int update_variant(int n);
+void set_update_variant(int n, int v);
+bool update_variant_known(int n);
+
 struct LineLaunch {
   int off = 0, count = 0, len = 0, max_lines = 0, inverse = 0;
 };
@@ -38,6 +44,7 @@ struct LineLaunch {
 // lists of every launch, and the captured graph that replays them.
 struct Executor {
   bool ready = false;
+  bool tuned = false;
   int ntiles = 0;
   int64_t NN_max = 0;
   int64_t total_updates = 0;
@@ -66,6 +73,10 @@ struct Executor {
   fpm_status setup(const std::vector<TilePlan>& tiles);
   hipError_t enqueue_sweep(hipStream_t s);
   hipError_t run(hipStream_t s, bool use_graph);
+  // time every update-kernel variant on this plan's largest launch of each
+  // tile size (before the state is initialised) and keep the fastest
+  hipError_t tune(hipStream_t s);
+  std::vector<float> tune_ms;  // [n class][variant] mean launch time of the last tuning
   // eager sweep with an event pair around each launch; per-kind totals
   hipError_t profile(hipStream_t s, fpm_kernel_time* out);
   // object_stage <- up^2 IFFT_N(shift(sigma S)) for every tile

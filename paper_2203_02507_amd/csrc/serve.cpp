@@ -290,7 +290,7 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
     const size_t b = ranges[i].second;
     const size_t cnt = (i + 1 < ranges.size() ? ranges[i + 1].second : flat.size()) - b;
     e = launch_update(ranges[i].first, tab, (const Item*)items.p + b, (int)cnt,
-                      nd_max[ranges[i].first], stream);
+                      nd_max[ranges[i].first], update_variant(ranges[i].first), stream);
   }
   if (e == hipSuccess && !st.empty())
     e = launch_pupil_reduce(tab, (const StepTile*)steps.p, (int)st.size(), n_max, stream);

@@ -189,3 +189,53 @@ def test_large_board_far_leds_match_oracle(fpm, orc):
     o_ref, P_ref, r_ref = oracle_run(orc, d, I)
     assert rel(o, o_ref) <= TOL_OBJ
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
+
+
+def test_uneven_batch_matches_oracle(fpm, orc):
+    """Uneven tiles in one plan: 64/96/128 px, 9x9..21x21 LEDs, upsampling 3-5,
+    their own defocus and position; iterations capped at 3 to keep the
+    oracle quick.  Every tile compared with the oracle."""
+    descs, Is = [], []
+    for td in fpm_synth.uneven_batch(T=40, sizes=(64, 96, 128)):
+        d = td.desc
+        for up in td.up_candidates:
+            d.upsample = up
+            if orc.offsets(d)[0] == 0:
+                break
+        else:
+            continue
+        d.iterations = min(d.iterations, 3)
+        _, _, I = orc.synthesize(td)
+        descs.append(d)
+        Is.append(I)
+        if len(descs) == 10:
+            break
+    assert {d.n for d in descs} == {64, 96, 128}
+    _, out = run_gpu(fpm, descs, Is)
+    for t, d in enumerate(descs):
+        o_ref, P_ref, r_ref = oracle_run(orc, d, Is[t])
+        o, P, r = out[t]
+        err = rel(o, o_ref)
+        print(f"tile {t} n {d.n} grid {d.led_rows} up {d.upsample}: rel L2 {err:.3e}")
+        assert err <= TOL_OBJ, t
+        assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
+
+
+def test_update_variants_bitwise_identical(fpm, orc, monkeypatch):
+    """The autotuner's variants differ only in LDS row padding: every variant
+    must give the same bits."""
+    tds = fpm_synth.full_fov_tiles(only=[3, 200], iterations=2, schedule=1, pupil_update=1)
+    descs, Is = [], []
+    for td in tds:
+        _, _, I = orc.synthesize(td, z_range=20.0)
+        descs.append(td.desc)
+        Is.append(I)
+    ref = None
+    for v in range(4):
+        monkeypatch.setenv("FPM_UPDATE_VARIANT", str(v))
+        _, out = run_gpu(fpm, descs, Is)
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert all(np.array_equal(x, y) for x, y in zip(a, b)), v
