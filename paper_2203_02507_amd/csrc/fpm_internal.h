@@ -109,3 +109,14 @@ hipError_t launch_gather(const TileDev* tiles, int count, void* dst, const int64
                          int which, int n_max, hipStream_t st);
 
 }  // namespace fpm
+
+namespace fpm {
+// MFMA precision variant (mfma.hip).  Tables of the centred DFT matrices per
+// (device, n, precision), built on first use and kept for the process.
+hipError_t dft_tables(int n, int prec, const uint16_t** E, const uint16_t** F);
+// side of the square support box the MFMA kernel covers for a support of
+// rows/columns [kx0, kx0 + nd)
+int mfma_box(int kx0, int nd);
+hipError_t launch_update_mfma(int n, int prec, const TileDev* tiles, const Item* items, int count,
+                              int box_max, const uint16_t* E, const uint16_t* F, hipStream_t st);
+}  // namespace fpm

@@ -241,10 +241,6 @@ fpm_status build_tile_plan(const fpm_tile_desc& d, TilePlan& tp, std::string& er
     err = "upsample must have no prime factor above 5 (1-6 or 8)";
     return FPM_E_ARG;
   }
-  if (d.precision != FPM_PREC_FP32_FFT) {
-    err = "precision not available in this build";
-    return FPM_E_UNSUPPORTED;
-  }
   tp.n = d.n;
   tp.N = d.n * d.upsample;
   tp.L = d.led_rows * d.led_cols;

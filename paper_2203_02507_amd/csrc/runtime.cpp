@@ -54,6 +54,13 @@ bool update_variant_known(int n) {
   return g_variant.count(n) != 0;
 }
 
+hipError_t launch_update_class(const Launch& l, const TileDev* tiles, const Item* items,
+                               hipStream_t st) {
+  if (l.prec == FPM_PREC_FP32_FFT)
+    return launch_update(l.n, tiles, items, l.count, l.nd_max, update_variant(l.n), st);
+  return launch_update_mfma(l.n, l.prec, tiles, items, l.count, l.box_max, l.tabE, l.tabF, st);
+}
+
 // ------------------------------------------------------------- DevBuf
 DevBuf::~DevBuf() {
   if (p) hipFree(p);
@@ -155,11 +162,23 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   std::vector<int> ids;
   launches.clear();
   int max_iter = 0, max_steps = 0;
+  // update classes: (n, precision) -> max support-column count, max MFMA box
+  std::map<std::pair<int, int>, std::pair<int, int>> uclass;
   std::map<int, int> nclass;  // n -> max nd
   for (const TilePlan& tp : tiles) {
     max_iter = std::max(max_iter, tp.d.iterations);
     max_steps = std::max(max_steps, tp.nsteps);
     nclass[tp.n] = std::max(nclass[tp.n], tp.nd);
+    auto& u = uclass[{tp.n, tp.d.precision}];
+    u.first = std::max(u.first, tp.nd);
+    u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
+  }
+  std::map<std::pair<int, int>, std::pair<const uint16_t*, const uint16_t*>> utabs;
+  for (auto& kv : uclass) {
+    if (kv.first.second == FPM_PREC_FP32_FFT) continue;
+    const uint16_t *E = nullptr, *F = nullptr;
+    if (!hip_ok(dft_tables(kv.first.first, kv.first.second, &E, &F), "DFT tables", &st)) return st;
+    utabs[kv.first] = {E, F};
   }
   int maxN = 0;
   for (const TilePlan& tp : tiles) maxN = std::max(maxN, tp.N);
@@ -206,15 +225,21 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
       continue;
     }
     for (int s = 0; s < max_steps; ++s) {
-      for (auto& kv : nclass) {
+      for (auto& kv : uclass) {
         Launch l{};
         l.kind = Launch::UPDATE;
-        l.n = kv.first;
-        l.nd_max = kv.second;
+        l.n = kv.first.first;
+        l.prec = kv.first.second;
+        l.nd_max = kv.second.first;
+        l.box_max = kv.second.second;
+        if (l.prec != FPM_PREC_FP32_FFT) {
+          l.tabE = utabs[kv.first].first;
+          l.tabF = utabs[kv.first].second;
+        }
         l.off = (int)items.size();
         for (int t : active) {
           const TilePlan& tp = tiles[t];
-          if (tp.n != kv.first || s >= tp.nsteps) continue;
+          if (tp.n != l.n || tp.d.precision != l.prec || s >= tp.nsteps) continue;
           for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
             const int j = tp.step_leds[m];
             Item it{};
@@ -477,7 +502,7 @@ hipError_t Executor::enqueue_sweep(hipStream_t s) {
         break;
       }
       case Launch::UPDATE:
-        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, update_variant(l.n), s);
+        e = launch_update_class(l, tab, it + l.off, s);
         break;
       case Launch::REDUCE:
         e = launch_pupil_reduce(tab, stp + l.off, l.count, l.n, s);
@@ -499,7 +524,8 @@ hipError_t Executor::tune(hipStream_t s) {
   const Item* it = (const Item*)items_d.p;
   std::map<int, const Launch*> biggest;
   for (const Launch& l : launches)
-    if (l.kind == Launch::UPDATE && (!biggest.count(l.n) || biggest[l.n]->count < l.count))
+    if (l.kind == Launch::UPDATE && l.prec == FPM_PREC_FP32_FFT &&
+        (!biggest.count(l.n) || biggest[l.n]->count < l.count))
       biggest[l.n] = &l;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);

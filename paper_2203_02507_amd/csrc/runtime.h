@@ -25,9 +25,18 @@ struct DevBuf {
 struct Launch {
   enum Kind { INIT, UPDATE, REDUCE, ITER_END, SMAX } kind = INIT;
   int n = 0, nd_max = 0;   // UPDATE: tile side, largest support-column count
+  int prec = 0;            // UPDATE: fpm_precision of every item of the launch
+  int box_max = 0;         // UPDATE, MFMA: largest support box
+  const uint16_t* tabE = nullptr;  // UPDATE, MFMA: DFT tables
+  const uint16_t* tabF = nullptr;
   int off = 0, count = 0;  // range in the item / step-tile / tile-id lists
   int iter = 0;            // ITER_END
 };
+
+// Launch one update class: the FP32 FFT kernel (prec 0, autotuned variant)
+// or the MFMA DFT kernel (prec 1, 2).
+hipError_t launch_update_class(const Launch& l, const TileDev* tiles, const Item* items,
+                               hipStream_t st);
 
 // Process-wide choice of update-kernel variant per tile size (autotuned on
 // first use; FPM_UPDATE_VARIANT=k forces one).

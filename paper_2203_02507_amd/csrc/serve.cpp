@@ -106,6 +106,13 @@ bool fpm_server_s::admit(Request* r, std::string& err) {
   const TilePlan& tp = r->plan;
   const size_t nn = (size_t)tp.n * tp.n, NN = (size_t)tp.N * tp.N;
   r->dev_bytes = footprint(tp, r->where);
+  if (tp.d.precision != FPM_PREC_FP32_FFT) {
+    const uint16_t *E = nullptr, *F = nullptr;  // built once per process and size
+    if (dft_tables(tp.n, tp.d.precision, &E, &F) != hipSuccess) {
+      err = "DFT tables";
+      return false;
+    }
+  }
   if (hipMalloc(&r->dev, r->dev_bytes) != hipSuccess) {
     err = "hipMalloc failed";
     return false;
@@ -242,8 +249,8 @@ hipError_t fpm_server_s::finish(Request* r) {
 
 // One scheduler tick: the next dependent step of every admitted request.
 hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
-  std::map<int, std::vector<Item>> by_n;
-  std::map<int, int> nd_max;
+  std::map<std::pair<int, int>, std::vector<Item>> by_n;  // (n, precision) classes
+  std::map<std::pair<int, int>, std::pair<int, int>> nd_max;  // class -> max nd, max MFMA box
   std::vector<StepTile> st;
   std::vector<int> ends;
   int n_max = 0;
@@ -258,9 +265,11 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
       it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
       it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
       it.slot = m - tp.step_beg[s];
-      by_n[tp.n].push_back(it);
+      by_n[{tp.n, tp.d.precision}].push_back(it);
     }
-    nd_max[tp.n] = std::max(nd_max[tp.n], tp.nd);
+    auto& mx = nd_max[{tp.n, tp.d.precision}];
+    mx.first = std::max(mx.first, tp.nd);
+    mx.second = std::max(mx.second, mfma_box(tp.kx0, tp.nd));
     n_max = std::max(n_max, tp.n);
     if (r->td.mode == 2) st.push_back(StepTile{r->slot, tp.step_beg[s + 1] - tp.step_beg[s]});
     if (s + 1 == tp.nsteps) ends.push_back(r->slot);
@@ -272,7 +281,7 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
   if (e != hipSuccess) return e;
   std::vector<Item> flat;
   flat.reserve(nitems);
-  std::vector<std::pair<int, size_t>> ranges;
+  std::vector<std::pair<std::pair<int, int>, size_t>> ranges;
   for (auto& kv : by_n) {
     ranges.emplace_back(kv.first, flat.size());
     flat.insert(flat.end(), kv.second.begin(), kv.second.end());
@@ -289,8 +298,15 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
   for (size_t i = 0; e == hipSuccess && i < ranges.size(); ++i) {
     const size_t b = ranges[i].second;
     const size_t cnt = (i + 1 < ranges.size() ? ranges[i + 1].second : flat.size()) - b;
-    e = launch_update(ranges[i].first, tab, (const Item*)items.p + b, (int)cnt,
-                      nd_max[ranges[i].first], update_variant(ranges[i].first), stream);
+    Launch l{};
+    l.kind = Launch::UPDATE;
+    l.n = ranges[i].first.first;
+    l.prec = ranges[i].first.second;
+    l.nd_max = nd_max[ranges[i].first].first;
+    l.box_max = nd_max[ranges[i].first].second;
+    l.count = (int)cnt;
+    if (l.prec != FPM_PREC_FP32_FFT) e = dft_tables(l.n, l.prec, &l.tabE, &l.tabF);
+    if (e == hipSuccess) e = launch_update_class(l, tab, (const Item*)items.p + b, stream);
   }
   if (e == hipSuccess && !st.empty())
     e = launch_pupil_reduce(tab, (const StepTile*)steps.p, (int)st.size(), n_max, stream);

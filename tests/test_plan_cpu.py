@@ -132,3 +132,22 @@ def test_server_without_gpu_fails_cleanly(fpm):
     with pytest.raises(fpm.FpmError) as e:
         fpm.Server(0, 4)
     assert e.value.status == fpm.FPM_E_ARG
+
+
+def test_precision_flags_plan_identically(fpm):
+    """The precision flag changes only the arithmetic of the transforms: the
+    plan tables of an MFMA tile are those of the FP32 tile; an unknown
+    precision is rejected."""
+    base = fpm_synth.full_fov_tiles(only=[17])[0].desc
+    plans = []
+    for prec in (0, 1, 2):
+        d = fpm_synth.full_fov_tiles(only=[17])[0].desc
+        d.precision = prec
+        plans.append(fpm.Plan([d]).tables(0))
+    for other in plans[1:]:
+        for a, b in zip(plans[0], other):
+            assert np.array_equal(a, b)
+    base.precision = 3
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([base])
+    assert e.value.status == fpm.FPM_E_ARG
