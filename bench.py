@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+MFMA_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 / fp16 matrix peak, vendor figure
+PREC_NAMES = {1: "mfma_bf16x3", 2: "mfma_fp16"}
+PREC_TERMS = {1: 3, 2: 1}    # real MFMA products per real product
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_02507_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernel_128_traffic.json")
 
@@ -93,6 +96,50 @@ def roofline(plan, prof):
             "kernel": f"update_kernel<{info.n}>", "bytes_per_update": b_upd,
             "updates_per_launch": round(per_launch_items, 1),
             "mean_launch_us": round(mean_s * 1e6, 2)}
+
+
+def mfma_flops_per_update(desc, prec):
+    """Matrix-core FLOPs one update issues in the MFMA kernel: 32x32x16 tile
+    steps of the four products (E Phi^T, E M1^T, F psi', F V^T) over the
+    support box, 4 real products per complex step, `terms` per real product."""
+    n = desc.n
+    R = math.floor(desc.na_obj * n * desc.pixel_um / desc.wavelength_um)
+    kx0, nd = n // 2 - R, 2 * R + 1
+    ub = kx0 & ~7
+    nk = (kx0 + nd - ub + 15) // 16
+    mt = (16 * nk + 31) // 32
+    W, KS = n // 32, n // 16
+    steps = W * nk * mt + W * nk * W + W * mt * KS + mt * mt * KS
+    dense = 16 * n * nd * (n + nd)   # unpadded complex DFT products on the support
+    return steps * 4 * 2 * 32 * 32 * 16 * PREC_TERMS[prec], dense * PREC_TERMS[prec]
+
+
+def oracle_objects(tds, I, plan, tiles):
+    """FP64 oracle reconstructions of sampled tiles on the same noisy data."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+
+    def one(t):
+        info = plan.infos[t]
+        Ih = I[info.intensity_offset:info.intensity_offset + info.L * info.n * info.n]
+        Ih = Ih.cpu().numpy().reshape(info.L, info.n, info.n)
+        r = oracle.reconstruct(tds[t].desc, Ih)
+        assert r.status == 0
+        return oracle.spectrum_to_object(tds[t].desc, r.S)
+
+    with ThreadPoolExecutor(len(tiles)) as ex:
+        return list(ex.map(one, tiles))
+
+
+def sample_errors(plan, obj, tiles, refs):
+    import numpy as np
+    out = []
+    for t, ref in zip(tiles, refs):
+        info = plan.infos[t]
+        o = obj[2 * info.object_offset:2 * (info.object_offset + info.N * info.N)]
+        o = o.cpu().numpy().view(np.complex64).reshape(info.N, info.N)
+        out.append(float(np.linalg.norm(o - ref) / np.linalg.norm(ref)))
+    return out
 
 
 def cpu_baseline(n_tiles: int = 8):
@@ -201,6 +248,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--precisions", default="1,2",
+                    help="MFMA precision variants timed beside the FP32 path (comma list, "
+                         "empty for none)")
+    ap.add_argument("--oracle-tiles", default="0,137",
+                    help="tiles whose result is compared with the FP64 oracle (empty: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -260,6 +312,58 @@ def main():
     log("kernel time per kind: " + json.dumps(prof))
     roof = roofline(plan, prof)
 
+    sample = [int(x) for x in args.oracle_tiles.split(",") if x.strip()]
+    sample = [t for t in sample if t < plan.ntiles]
+    refs = None
+    errs = {}
+    if sample:
+        t1 = time.perf_counter()
+        refs = oracle_objects(tds, I, plan, sample)
+        log(f"oracle on tiles {sample}: {time.perf_counter() - t1:.1f} s")
+        errs["fp32_fft"] = sample_errors(plan, obj, sample, refs)
+
+    mfma = {}
+    for prec in [int(x) for x in args.precisions.split(",") if x.strip()]:
+        for td in tds:
+            td.desc.precision = prec
+        plan_p = fpm.Plan([td.desc for td in tds])
+        for w in range(args.warmup):
+            fpm.fpm_reconstruct(plan_p, I, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            fpm.fpm_reconstruct(plan_p, I, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        if sample:
+            errs[PREC_NAMES[prec]] = sample_errors(plan_p, obj, sample, refs)
+        prof_p = fpm.fpm_profile_reconstruct(plan_p, I)
+        torch.cuda.synchronize()
+        upd = prof_p["update"]
+        issued, dense = mfma_flops_per_update(tds[0].desc, prec)
+        per_launch = upd["items"] / max(upd["launches"], 1)
+        mean_s = upd["total_ms"] / 1e3 / max(upd["launches"], 1)
+        achieved = issued * per_launch / mean_s / 1e12
+        mfma[PREC_NAMES[prec]] = {
+            "value": round(updates / (ms / 1e3), 1), "unit": "updates/s",
+            "ms_per_step": round(ms, 3),
+            "vs_fp32": round(ms_per_step / ms, 3),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 1),
+                         "peak": MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                         "kernel": f"mfma_update_kernel<{tds[0].desc.n}>",
+                         "mfma_flops_per_update": issued,
+                         "dense_dft_flops_per_update": dense,
+                         "updates_per_launch": round(per_launch, 1),
+                         "mean_launch_us": round(mean_s * 1e6, 2)},
+            "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof_p.items()},
+        }
+        log(f"{PREC_NAMES[prec]}: " + json.dumps(mfma[PREC_NAMES[prec]]))
+        del plan_p
+    for td in tds:
+        td.desc.precision = 0
+
     serving = None
     if not args.no_serving:
         serving = serving_bench(fpm)
@@ -290,6 +394,8 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mfma": mfma,
+        "rel_l2_vs_oracle": {"tiles": sample, **errs} if sample else None,
         "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
     }
