@@ -50,6 +50,10 @@ typedef enum {
   FPM_E_UNSUPPORTED = -7  /* tile size or precision this build does not run   */
 } fpm_status;
 
+/* Arithmetic of the two n x n transforms of every update.  The MFMA forms
+ * compute them as dense products with centred DFT matrices on the matrix
+ * cores with FP32 accumulation (tile sides 64, 96, 128; FPM_E_UNSUPPORTED
+ * for 256); the plan, the update rule and every other step are unchanged. */
 typedef enum {
   FPM_PREC_FP32_FFT = 0,     /* FP32 FFTs in LDS and registers (default)    */
   FPM_PREC_MFMA_BF16X3 = 1,  /* dense DFT on MFMA, three-term split bf16    */
@@ -84,7 +88,7 @@ typedef enum { FPM_MEM_HOST = 0, FPM_MEM_DEVICE = 1 } fpm_mem;
  *   [N/2 + drow - n/2, +n), cols [N/2 + dcol - n/2, +n); |drow|, |dcol| must
  *   not exceed (N - n)/2, else FPM_E_GEOMETRY. */
 typedef struct {
-  int32_t n;              /* LR tile side in pixels: 64, 96 or 128 (even)     */
+  int32_t n;              /* LR tile side in pixels: 64, 96, 128 or 256       */
   int32_t upsample;       /* HR side N = n * upsample                         */
   int32_t led_rows, led_cols;
   double led_pitch_um, led_height_um;

@@ -71,10 +71,16 @@ struct StepTile {  // a tile that ran a group in this step
 // `variant` selects the LDS row padding of the transpose buffer
 // (0: 16, 1: 1, 2: 8, 3: 32 complex elements); results are identical.
 constexpr int kUpdateVariants = 4;
+// n = 256 runs a persistent kernel whose workgroups keep their transposes in
+// `big_scratch`: kBigSlots slots of n * n complex values (kBigSlots * 512 KiB);
+// ignored for n <= 128.
+constexpr int kBigSlots = 256;
+constexpr size_t big_scratch_bytes(int n) { return (size_t)kBigSlots * n * n * 8; }
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         int variant, hipStream_t st);
+                         int variant, float2* big_scratch, hipStream_t st);
 hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
-                               float* out, const int64_t* out_off, int nd_max, hipStream_t st);
+                               float* out, const int64_t* out_off, int nd_max,
+                               float2* big_scratch, hipStream_t st);
 hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
                                hipStream_t st);
 hipError_t launch_iter_end(const TileDev* tiles, const int* tile_ids, int count, int iter,

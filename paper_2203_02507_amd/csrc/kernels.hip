@@ -340,6 +340,74 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
   }
 }
 
+// Modulus projection of one row segment and its residual partials.
+// a[k] holds psi at (row `line`, column xc + k) of the unshifted frame.
+template <int R>
+__device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[R], int line,
+                                            int xc, float& e_acc, float& i_acc) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float I = ipre[k];
+    const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+    // psi' = m psi / |psi| through the hardware reciprocal square root, which
+    // flushes denormal inputs: a field whose |psi|^2 is below 2^-100 is
+    // first scaled by 2^100 (exact), so every nonzero psi keeps its phase.
+    // Where psi = 0 the method sets psi' = sqrt(I) in the centred frame; this
+    // frame differs from it by (-1)^(x+y), so the zero-field value is
+    // (-1)^(x+y) sqrt(I) here.
+    const float m_zero = ((line + xc + k) & 1) ? -m : m;
+    const float p2 = cabs2(a[k]);
+    const bool small = p2 < 0x1p-100f;
+    const float2 as = small ? cscale(a[k], 0x1p100f) : a[k];
+    const float p2s = small ? cabs2(as) : p2;
+    const bool live = p2s > 0.0f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(p2s) : 0.0f;
+    const float amp = p2s * rinv * (small ? 0x1p-100f : 1.0f);
+    const float d = amp - m;
+    e_acc = fmaf(d, d, e_acc);
+    i_acc += I;
+    const float s = m * rinv;
+    a[k] = live ? cscale(as, s) : make_float2(m_zero, 0.0f);
+  }
+}
+
+// Spectrum (and pupil) update of one support column kx: a[k] = Phi'(ky =
+// q + 4k, kx).  S_stored += conj(P) D / (max|P|^2 sigma); the pupil step
+// conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
+// goes to P (mode 1) or to the increment slot (mode 2).
+template <int n>
+__device__ __forceinline__ void update_column(const float2 (&a)[n / kQ],
+                                              __amdgpu_buffer_rsrc_t Sw,
+                                              __amdgpu_buffer_rsrc_t Pw,
+                                              __amdgpu_buffer_rsrc_t Dw, int N, int kx, int2 ch,
+                                              int q, float sigf, float pmax2, float smax,
+                                              int mode) {
+  constexpr int R = n / kQ;
+  const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
+  const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
+  const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
+  const bool upd_s = pmax2 > 0.0f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ky = q + kQ * k;
+    const bool in = ky >= ch.x && ky <= ch.y;
+    const int offS = in ? s0 + k * (kQ * 8) * N : kOob;
+    const int offP = in ? p0 + k * (kQ * 8 * n) : kOob;
+    const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
+    const float2 pv = bload2(Pw, offP);
+    const float2 phi = cscale(cmul(pv, xs), sigf);
+    const float2 d = csub(a[k], phi);
+    bstore2(Sw, upd_s ? offS : kOob, cadd(xs, cscale(cmulc(d, pv), inv_ps)));
+    if (mode != 0) {
+      const float2 dp = cscale(cmulc(d, xs), inv_ss);
+      if (mode == 1)
+        bstore2(Pw, offP, cadd(pv, dp));
+      else
+        bstore2(Dw, offP, dp);
+    }
+  }
+}
+
 }  // namespace
 
 // ===================================================== the update kernel
@@ -415,30 +483,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
 
   // ---- modulus constraint + residual partials (row `line`, x = xc + k)
   float e_acc = 0.0f, i_acc = 0.0f;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const float I = ipre[k];
-    const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
-    // psi' = m psi / |psi| through the hardware reciprocal square root, which
-    // flushes denormal inputs: a field whose |psi|^2 is below 2^-100 is
-    // first scaled by 2^100 (exact), so every nonzero psi keeps its phase.
-    // Where psi = 0 the method sets psi' = sqrt(I) in the centred frame; this
-    // frame differs from it by (-1)^(x+y), so the zero-field value is
-    // (-1)^(x+y) sqrt(I) here.
-    const float m_zero = ((line + xc + k) & 1) ? -m : m;
-    const float p2 = cabs2(a[k]);
-    const bool small = p2 < 0x1p-100f;
-    const float2 as = small ? cscale(a[k], 0x1p100f) : a[k];
-    const float p2s = small ? cabs2(as) : p2;
-    const bool live = p2s > 0.0f;
-    const float rinv = live ? __builtin_amdgcn_rsqf(p2s) : 0.0f;
-    const float amp = p2s * rinv * (small ? 0x1p-100f : 1.0f);
-    const float d = amp - m;
-    e_acc = fmaf(d, d, e_acc);
-    i_acc += I;
-    const float s = m * rinv;
-    a[k] = live ? cscale(as, s) : make_float2(m_zero, 0.0f);
-  }
+  modulus_row<R>(a, ipre, line, xc, e_acc, i_acc);
   {
     double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
     if ((tid & 63) == 0) {
@@ -468,31 +513,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
 #pragma unroll
     for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
     const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
-    const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
-    const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
-    const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
-    const bool upd_s = pmax2 > 0.0f;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int ky = q + kQ * k;
-      const bool in = ky >= ch.x && ky <= ch.y;
-      const int offS = in ? s0 + k * (kQ * 8) * N : kOob;
-      const int offP = in ? p0 + k * (kQ * 8 * n) : kOob;
-      const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
-      const float2 pv = bload2(Pw, offP);
-      const float2 phi = cscale(cmul(pv, xs), sigf);
-      const float2 d = csub(a[k], phi);
-      // S_stored += conj(P) D / (max|P|^2 sigma)
-      bstore2(Sw, upd_s ? offS : kOob, cadd(xs, cscale(cmulc(d, pv), inv_ps)));
-      if (mode != 0) {
-        // dP = conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
-        const float2 dp = cscale(cmulc(d, xs), inv_ss);
-        if (mode == 1)
-          bstore2(Pw, offP, cadd(pv, dp));
-        else
-          bstore2(Dw, offP, dp);
-      }
-    }
+    update_column<n>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode);
   }
 
   if (tid == 0) {
@@ -546,6 +567,192 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
   for (int v = 0; v < R / 4; ++v)
     dst[v] = make_float4(cabs2(a[4 * v]), cabs2(a[4 * v + 1]), cabs2(a[4 * v + 2]),
                          cabs2(a[4 * v + 3]));
+}
+
+// ============================== sides whose transposes exceed LDS (n = 256)
+// Persistent form of the update: 512 threads run the lines of each phase in
+// 4n/512 rounds (R = n/4 points per thread, as above), the two transposes go
+// through this workgroup's own slot of global scratch ([nd][n] complex, the
+// same layout as the LDS buffer), and each workgroup loops over items
+// blockIdx.x, blockIdx.x + gridDim.x, ...  Phase B writes the support
+// columns of its rows back into the slot in place: a thread reads and writes
+// only columns of one residue mod 4 of its own row, so no other thread's
+// input is overwritten.
+constexpr int kBigThreads = 512;
+
+template <int n>
+__global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
+                                                                 const Item* __restrict__ items,
+                                                                 int count,
+                                                                 float2* __restrict__ scratch) {
+  constexpr int R = n / kQ;
+  constexpr int NT = kBigThreads;
+  constexpr int LPR = NT / kQ;       // lines per round
+  constexpr int ROUNDS = n / LPR;
+  constexpr int NW = NT / 64;
+  __shared__ float2 tw[n];
+  __shared__ float red_pmax[NW];
+  __shared__ double red_e[NW], red_i[NW];
+  const int tid = threadIdx.x;
+  const int q = tid & 3, l0 = tid >> 2;
+  const int wave = tid >> 6;
+  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
+  const int xc = R * brev2(q);
+  __syncthreads();
+
+  for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+    const Item it = items[ii];
+    const TileDev t = tiles[it.tile];
+    const int N = t.N;
+    const size_t woff = (size_t)it.wy0 * N + it.wx0;
+    const __amdgpu_buffer_rsrc_t Sw = make_rsrc(t.S + woff, (unsigned)(((size_t)N * N - woff) * 8));
+    const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
+    const __amdgpu_buffer_rsrc_t Iw = make_rsrc(t.I + (size_t)it.led * n * n, n * n * 4);
+    const __amdgpu_buffer_rsrc_t Dw = make_rsrc(t.dP + (size_t)it.slot * n * n, n * n * 8);
+    const float sigf = (float)*t.sigma;
+    float2 a[R];
+
+    // ---- phase A: support columns, IFFT along ky, to the scratch slot
+    float pm = 0.0f;
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      if (line < t.nd) {
+        const int kx = t.kx0 + line;
+        pm = fmaxf(pm, gather_phi<n>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
+        line_dit<n, true>(a, q, tw);
+        float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k)
+          dst[k] = make_float4(a[2 * k].x, a[2 * k].y, a[2 * k + 1].x, a[2 * k + 1].y);
+      }
+    }
+    pm = wave_max(pm);
+    if ((tid & 63) == 0) red_pmax[wave] = pm;
+    __syncthreads();
+
+    // ---- phase B: rows, IFFT along kx, modulus, FFT along x
+    float e_acc = 0.0f, i_acc = 0.0f;
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      load_rows<n, 0>(sb, t.kx0, t.nd, line, q, a);
+      line_dit<n, true>(a, q, tw);
+      float iv[R];
+#pragma unroll
+      for (int v = 0; v < R / 4; ++v) {
+        const v4f f = __builtin_amdgcn_raw_buffer_load_b128(Iw, (line * n + xc + 4 * v) * 4, 0, 0);
+        iv[4 * v] = f.x;
+        iv[4 * v + 1] = f.y;
+        iv[4 * v + 2] = f.z;
+        iv[4 * v + 3] = f.w;
+      }
+      modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
+      line_dif<n, false>(a, q, tw);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int c = q + kQ * k - t.kx0;
+        if (c >= 0 && c < t.nd) sb[(size_t)c * n + line] = a[k];
+      }
+    }
+    {
+      const double e = wave_sum((double)e_acc), s = wave_sum((double)i_acc);
+      if ((tid & 63) == 0) {
+        red_e[wave] = e;
+        red_i[wave] = s;
+      }
+    }
+    __syncthreads();
+
+    // ---- phase A': support columns, FFT along y, update
+    float pmax2 = red_pmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
+    const float smax = __uint_as_float(*t.smax);
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      if (line < t.nd) {
+        const float4* src = reinterpret_cast<const float4*>(sb + (size_t)line * n + xc);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+          const float4 f = src[k];
+          a[2 * k] = make_float2(f.x, f.y);
+          a[2 * k + 1] = make_float2(f.z, f.w);
+        }
+        line_dif<n, false>(a, q, tw);
+        const int kx = t.kx0 + line;
+        update_column<n>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
+      }
+    }
+    if (tid == 0) {
+      double e = 0.0, s = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        e += red_e[w];
+        s += red_i[w];
+      }
+      t.e_part[it.led] = e;
+      t.i_part[it.led] = s;
+    }
+    __syncthreads();  // the slot and the reduction arrays are reused by the next item
+  }
+}
+
+// forward model for the same sides: phases A and B, |psi|^2 out
+template <int n>
+__global__ __launch_bounds__(kBigThreads) void forward_kernel_big(const TileDev* __restrict__ tiles,
+                                                                  const Item* __restrict__ items,
+                                                                  int count, float* __restrict__ out,
+                                                                  const int64_t* __restrict__ out_off,
+                                                                  float2* __restrict__ scratch) {
+  constexpr int R = n / kQ;
+  constexpr int NT = kBigThreads;
+  constexpr int LPR = NT / kQ;
+  constexpr int ROUNDS = n / LPR;
+  __shared__ float2 tw[n];
+  const int tid = threadIdx.x;
+  const int q = tid & 3, l0 = tid >> 2;
+  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
+  const int xc = R * brev2(q);
+  __syncthreads();
+  for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+    const Item it = items[ii];
+    const TileDev t = tiles[it.tile];
+    const size_t woff = (size_t)it.wy0 * t.N + it.wx0;
+    const __amdgpu_buffer_rsrc_t Sw =
+        make_rsrc(t.S + woff, (unsigned)(((size_t)t.N * t.N - woff) * 8));
+    const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
+    float2 a[R];
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      if (line < t.nd) {
+        const int kx = t.kx0 + line;
+        gather_phi<n>(Sw, Pw, t.N, kx, t.chord[kx], q, 1.0f / (float)(n * n), a);
+        line_dit<n, true>(a, q, tw);
+        float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k)
+          dst[k] = make_float4(a[2 * k].x, a[2 * k].y, a[2 * k + 1].x, a[2 * k + 1].y);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      load_rows<n, 0>(sb, t.kx0, t.nd, line, q, a);
+      line_dit<n, true>(a, q, tw);
+      float4* dst = reinterpret_cast<float4*>(out + out_off[it.tile] + (size_t)it.led * n * n +
+                                              (size_t)line * n + xc);
+#pragma unroll
+      for (int v = 0; v < R / 4; ++v)
+        dst[v] = make_float4(cabs2(a[4 * v]), cabs2(a[4 * v + 1]), cabs2(a[4 * v + 2]),
+                             cabs2(a[4 * v + 3]));
+    }
+    __syncthreads();
+  }
 }
 
 // ============================================== pupil mean of a group
@@ -874,9 +1081,16 @@ void set_lds_limits() {
 }  // namespace
 
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         int variant, hipStream_t st) {
+                         int variant, float2* big_scratch, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   set_lds_limits();
+  if (n == 256) {
+    if (!big_scratch) return hipErrorInvalidValue;
+    const int grid = count < kBigSlots ? count : kBigSlots;
+    hipLaunchKernelGGL(update_kernel_big<256>, dim3(grid), dim3(kBigThreads), 0, st, tiles, items,
+                       count, big_scratch);
+    return hipGetLastError();
+  }
   switch (n) {
     case 64: return launch_update_n<64>(tiles, items, count, nd_max, variant, st);
     case 96: return launch_update_n<96>(tiles, items, count, nd_max, variant, st);
@@ -886,9 +1100,17 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
 }
 
 hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
-                               float* out, const int64_t* out_off, int nd_max, hipStream_t st) {
+                               float* out, const int64_t* out_off, int nd_max,
+                               float2* big_scratch, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   set_lds_limits();
+  if (n == 256) {
+    if (!big_scratch) return hipErrorInvalidValue;
+    const int grid = count < kBigSlots ? count : kBigSlots;
+    hipLaunchKernelGGL(forward_kernel_big<256>, dim3(grid), dim3(kBigThreads), 0, st, tiles, items,
+                       count, out, out_off, big_scratch);
+    return hipGetLastError();
+  }
   switch (n) {
     case 64: return launch_forward_n<64>(tiles, items, count, out, out_off, nd_max, st);
     case 96: return launch_forward_n<96>(tiles, items, count, out, out_off, nd_max, st);

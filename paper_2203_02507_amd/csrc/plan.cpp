@@ -214,8 +214,12 @@ void build_steps(TilePlan& tp) {
 fpm_status build_tile_plan(const fpm_tile_desc& d, TilePlan& tp, std::string& err) {
   tp = TilePlan{};
   tp.d = d;
-  if (d.n != 64 && d.n != 96 && d.n != 128) {
-    err = "tile side n must be 64, 96 or 128";
+  if (d.n != 64 && d.n != 96 && d.n != 128 && d.n != 256) {
+    err = "tile side n must be 64, 96, 128 or 256";
+    return FPM_E_UNSUPPORTED;
+  }
+  if (d.n == 256 && d.precision != FPM_PREC_FP32_FFT) {
+    err = "the MFMA precision variant runs tile sides 64, 96 and 128";
     return FPM_E_UNSUPPORTED;
   }
   if (d.upsample < 1 || d.upsample > 8 || d.led_rows < 1 || d.led_cols < 1 ||

@@ -57,7 +57,8 @@ bool update_variant_known(int n) {
 hipError_t launch_update_class(const Launch& l, const TileDev* tiles, const Item* items,
                                hipStream_t st) {
   if (l.prec == FPM_PREC_FP32_FFT)
-    return launch_update(l.n, tiles, items, l.count, l.nd_max, update_variant(l.n), st);
+    return launch_update(l.n, tiles, items, l.count, l.nd_max, update_variant(l.n), l.big_scratch,
+                         st);
   return launch_update_mfma(l.n, l.prec, tiles, items, l.count, l.box_max, l.tabE, l.tabF, st);
 }
 
@@ -173,6 +174,9 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     u.first = std::max(u.first, tp.nd);
     u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
   }
+  if (nclass.count(256) &&
+      !hip_ok(big_scratch.alloc(big_scratch_bytes(256)), "hipMalloc(transpose slots)", &st))
+    return st;
   std::map<std::pair<int, int>, std::pair<const uint16_t*, const uint16_t*>> utabs;
   for (auto& kv : uclass) {
     if (kv.first.second == FPM_PREC_FP32_FFT) continue;
@@ -232,6 +236,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
         l.prec = kv.first.second;
         l.nd_max = kv.second.first;
         l.box_max = kv.second.second;
+        if (l.n == 256) l.big_scratch = (float2*)big_scratch.p;
         if (l.prec != FPM_PREC_FP32_FFT) {
           l.tabE = utabs[kv.first].first;
           l.tabF = utabs[kv.first].second;
@@ -524,7 +529,7 @@ hipError_t Executor::tune(hipStream_t s) {
   const Item* it = (const Item*)items_d.p;
   std::map<int, const Launch*> biggest;
   for (const Launch& l : launches)
-    if (l.kind == Launch::UPDATE && l.prec == FPM_PREC_FP32_FFT &&
+    if (l.kind == Launch::UPDATE && l.prec == FPM_PREC_FP32_FFT && l.n != 256 &&
         (!biggest.count(l.n) || biggest[l.n]->count < l.count))
       biggest[l.n] = &l;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -538,10 +543,10 @@ hipError_t Executor::tune(hipStream_t s) {
     int best = 0;
     float best_ms = 1e30f;
     for (int v = 0; v < kUpdateVariants && e == hipSuccess; ++v) {
-      e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, s);  // warm-up
+      e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       for (int r = 0; r < 3 && e == hipSuccess; ++r)
-        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, s);
+        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -622,7 +627,7 @@ hipError_t Executor::enqueue_forward(const float2* obj_src, float* out, hipStrea
   for (const FwdLaunch& fl : fwd_launches) {
     if (e != hipSuccess) return e;
     e = launch_forward_leds(fl.n, ft, (const Item*)fwd_items.p + fl.off, fl.count, out,
-                            (const int64_t*)i_off_d.p, fl.nd_max, s);
+                            (const int64_t*)i_off_d.p, fl.nd_max, (float2*)big_scratch.p, s);
   }
   return e;
 }
@@ -630,7 +635,7 @@ hipError_t Executor::enqueue_forward(const float2* obj_src, float* out, hipStrea
 size_t Executor::device_bytes() const {
   const DevBuf* all[] = {&state, &table, &items_d, &steps_d, &ids_d, &jobs_d, &i_off_d, &o_off_d,
                          &p_off_d, &r_off_d, &obj_stage, &fwd_P, &fwd_table, &fwd_items,
-                         &I_stage, &res_stage, &pupil_stage};
+                         &I_stage, &res_stage, &pupil_stage, &big_scratch};
   size_t b = 0;
   for (const DevBuf* d : all) b += d->bytes;
   return b;

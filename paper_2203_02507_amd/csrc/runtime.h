@@ -29,6 +29,7 @@ struct Launch {
   int box_max = 0;         // UPDATE, MFMA: largest support box
   const uint16_t* tabE = nullptr;  // UPDATE, MFMA: DFT tables
   const uint16_t* tabF = nullptr;
+  float2* big_scratch = nullptr;   // UPDATE, n = 256: transpose slots
   int off = 0, count = 0;  // range in the item / step-tile / tile-id lists
   int iter = 0;            // ITER_END
 };
@@ -69,6 +70,7 @@ struct Executor {
   int n_max = 0;
   // object finalise / forward staging: complex [total_obj], pupil [total_pupil]
   DevBuf obj_stage, fwd_P, fwd_table, fwd_items, I_stage, res_stage, pupil_stage;
+  DevBuf big_scratch;  // transpose slots of the n = 256 kernels (allocated if used)
   std::vector<LineLaunch> fin_line_launches, fwd_line_launches;
   struct FwdLaunch {
     int n, nd_max, off, count;

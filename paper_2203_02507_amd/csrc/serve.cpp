@@ -91,6 +91,7 @@ struct fpm_server_s {
   std::thread worker;
   // device tables rebuilt per tick
   DevBuf table, items, steps, ids, jobs;
+  DevBuf big_scratch;  // transpose slots of the n = 256 kernel, allocated on first use
   std::vector<int> free_slots;
   std::vector<TileDev> host_table;
   fpm_status fatal = FPM_OK;
@@ -306,6 +307,10 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
     l.box_max = nd_max[ranges[i].first].second;
     l.count = (int)cnt;
     if (l.prec != FPM_PREC_FP32_FFT) e = dft_tables(l.n, l.prec, &l.tabE, &l.tabF);
+    if (e == hipSuccess && l.n == 256) {
+      e = big_scratch.alloc(big_scratch_bytes(256));
+      l.big_scratch = (float2*)big_scratch.p;
+    }
     if (e == hipSuccess) e = launch_update_class(l, tab, (const Item*)items.p + b, stream);
   }
   if (e == hipSuccess && !st.empty())

@@ -151,3 +151,23 @@ def test_precision_flags_plan_identically(fpm):
     with pytest.raises(fpm.FpmError) as e:
         fpm.Plan([base])
     assert e.value.status == fpm.FPM_E_ARG
+
+
+def test_n256_plan_tables_and_precision(fpm, orc):
+    """256-px tiles plan like the others (tables bit-exact with the oracle);
+    the MFMA variant does not run them."""
+    rng = np.random.default_rng(256)
+    descs = []
+    for k in range(3):
+        d = fpm_synth.TileDesc(n=256, upsample=3 + k % 2, led_rows=9 + 4 * k, led_cols=9 + 4 * k,
+                               tile_x_um=float(rng.uniform(-1500, 1500)),
+                               tile_y_um=float(rng.uniform(-1500, 1500)),
+                               defocus_um=float(rng.uniform(-30, 30)))
+        if orc.offsets(d)[0] == 0:
+            descs.append(d)
+    assert descs
+    _check_tables(fpm, orc, descs)
+    d = fpm_synth.TileDesc(n=256, upsample=3, led_rows=9, led_cols=9, precision=1)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.Plan([d])
+    assert e.value.status == fpm.FPM_E_UNSUPPORTED
