@@ -166,17 +166,132 @@ def cpu_baseline(n_tiles: int = 8):
                       f"workload ({updates} updates, {wall:.1f} s wall)"}
 
 
+def pick_upsample(fpm, td):
+    d = td.desc
+    for up in td.up_candidates:
+        d.upsample = up
+        try:
+            fpm.Plan([d])
+            return True
+        except fpm.FpmError:
+            pass
+    return False
+
+
+def uneven_objects(tds, device):
+    """Seeded objects of every tile (host threads), packed on the device."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import torch
+    import fpm_synth
+
+    total = sum(td.desc.N ** 2 for td in tds)
+    o = torch.empty(2 * total, dtype=torch.float32, device=device)
+    offs, acc = [], 0
+    for td in tds:
+        offs.append(acc)
+        acc += td.desc.N ** 2
+
+    def one(k):
+        td = tds[k]
+        return k, fpm_synth.random_object(td.rng, td.desc.N).astype(np.complex64)
+
+    with ThreadPoolExecutor(16) as ex:
+        for k, obj in ex.map(one, range(len(tds))):
+            sl = o[2 * offs[k]:2 * (offs[k] + tds[k].desc.N ** 2)]
+            sl.copy_(torch.from_numpy(obj.reshape(-1).view(np.float32)))
+    return o
+
+
+def uneven_bench(fpm, T: int, steps: int, warmup: int, sample: int = 16):
+    """Batched form: T uneven tiles (n in {64, 96, 128, 256}, 9x9..21x21 LEDs,
+    upsampling 3-5, 5-30 iterations, defocus, 1e3-1e5 photons) in one plan,
+    one launch per (size, step) over all tiles, replayed from a graph.  Beside
+    it, the first `sample` tiles run one plan per tile (no batching across
+    tiles) and as one plan, so the batching gain is measured on equal work."""
+    import torch
+    import fpm_synth
+
+    device = "cuda"
+    t0 = time.perf_counter()
+    tds = [td for td in fpm_synth.uneven_batch(T=T, sizes=(64, 96, 128, 256))
+           if pick_upsample(fpm, td)]
+    plan = fpm.Plan([td.desc for td in tds])
+    o = uneven_objects(tds, device)
+    I = torch.empty(plan.total_intensity, dtype=torch.float32, device=device)
+    fpm.fpm_forward(plan, o, None, I, fpm.FPM_MEM_DEVICE)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(fpm_synth.ROOT_SEED + 3)
+    for t, info in enumerate(plan.infos):
+        sl = I[info.intensity_offset:info.intensity_offset + info.L * info.n * info.n]
+        c = tds[t].peak_photons / max(float(sl.max()), 1e-30)
+        sl.copy_(torch.poisson(sl.clamp_min(0) * c, generator=gen) / c)
+    del o
+    torch.cuda.synchronize()
+    log(f"uneven inputs: {len(tds)} tiles, {I.numel() * 4 / 2**30:.2f} GiB in "
+        f"{time.perf_counter() - t0:.1f} s")
+    obj, pup, res = fpm.device_buffers(plan, device)
+    updates = sum(i.L * i.iterations for i in plan.infos)
+
+    def timed(pl, Iv, k):
+        for _ in range(warmup):
+            fpm.fpm_reconstruct(pl, Iv, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fpm.fpm_reconstruct(pl, Iv, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms = timed(plan, I, steps)
+    prof = fpm.fpm_profile_reconstruct(plan, I)
+    torch.cuda.synchronize()
+    by_n = {}
+    for i in plan.infos:
+        b = by_n.setdefault(str(i.n), {"tiles": 0, "updates": 0})
+        b["tiles"] += 1
+        b["updates"] += i.L * i.iterations
+    # batching gain on the first `sample` tiles
+    ns = min(sample, len(tds))
+    sub = fpm.Plan([td.desc for td in tds[:ns]])
+    sub_I = torch.cat([I[i.intensity_offset:i.intensity_offset + i.L * i.n * i.n]
+                       for i in plan.infos[:ns]])
+    sub_updates = sum(i.L * i.iterations for i in plan.infos[:ns])
+    ms_batched = timed(sub, sub_I, 1)
+    ms_single = 0.0
+    for k in range(ns):
+        one = fpm.Plan([tds[k].desc])
+        info = plan.infos[k]
+        ms_single += timed(one, I[info.intensity_offset:info.intensity_offset +
+                                  info.L * info.n * info.n], 1)
+    return {"tiles": len(tds), "updates_per_step": updates, "ms_per_step": round(ms, 3),
+            "value": round(updates / (ms / 1e3), 1), "unit": "updates/s", "by_n": by_n,
+            "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
+            "update_launches": prof["update"]["launches"],
+            "batching_gain": {"tiles": ns, "updates": sub_updates,
+                              "one_plan_ms": round(ms_batched, 3),
+                              "plan_per_tile_ms": round(ms_single, 3),
+                              "speedup": round(ms_single / ms_batched, 2)}}
+
+
 def serving_bench(fpm, n_req: int = 48, load: float = 0.8, seed: int = 5):
-    """Requests shaped like single uneven tiles (64/128 px, 9x9..21x21 LEDs,
-    5..30 iterations) arriving as a Poisson stream at `load` x the saturated
-    request rate measured closed-loop; p50/p99 latency and sustained updates/s."""
+    """Requests shaped like single uneven tiles (64-256 px, 9x9..21x21 LEDs,
+    5..30 iterations; precision flags 50 % FP32, 25 % BF16x3, 25 % FP16 on
+    the sizes the MFMA form runs) arriving as a Poisson stream at `load` x the
+    saturated request rate measured closed-loop; p50/p99 latency and
+    sustained updates/s."""
     import numpy as np
     import torch
     import fpm_synth
 
     reqs = []
-    for td in fpm_synth.uneven_batch(T=4 * n_req, workload=4, sizes=(64, 128)):
+    mix_rng = np.random.default_rng(seed)
+    for td in fpm_synth.uneven_batch(T=4 * n_req, workload=4, sizes=(64, 96, 128, 256)):
         d = td.desc
+        if d.n <= 128:
+            d.precision = int(mix_rng.choice([0, 0, 1, 2]))
         for up in td.up_candidates:
             d.upsample = up
             try:
@@ -235,7 +350,10 @@ def serving_bench(fpm, n_req: int = 48, load: float = 0.8, seed: int = 5):
             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
             "sustained_updates_per_s": round(upd / (last - first), 1),
-            "mix": "64/128 px tiles, 81-441 LEDs, 5-30 iterations, FP32"}
+            "mix": "64-256 px tiles, 81-441 LEDs, 5-30 iterations, precision 50 % FP32, "
+                   "25 % BF16x3, 25 % FP16 (FP32 for 256 px)",
+            "precisions": {str(p): sum(1 for d, _ in reqs if d.precision == p)
+                           for p in (0, 1, 2)}}
 
 
 def main():
@@ -253,6 +371,8 @@ def main():
                          "empty for none)")
     ap.add_argument("--oracle-tiles", default="0,137",
                     help="tiles whose result is compared with the FP64 oracle (empty: none)")
+    ap.add_argument("--uneven-tiles", type=int, default=512,
+                    help="tiles of the uneven batched workload (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -364,6 +484,11 @@ def main():
     for td in tds:
         td.desc.precision = 0
 
+    uneven = None
+    if args.uneven_tiles > 0:
+        uneven = uneven_bench(fpm, args.uneven_tiles, steps=1, warmup=1)
+        log("uneven batch: " + json.dumps(uneven))
+
     serving = None
     if not args.no_serving:
         serving = serving_bench(fpm)
@@ -396,6 +521,7 @@ def main():
         "cpu_baseline": cpu,
         "mfma": mfma,
         "rel_l2_vs_oracle": {"tiles": sample, **errs} if sample else None,
+        "uneven_batch": uneven,
         "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
     }

@@ -27,7 +27,7 @@ namespace fpm {
 
 namespace {
 
-constexpr int kQ = 4;  // threads per line
+constexpr int kQ = 4;  // lanes per line of the default layout (Q = 8 also exists)
 
 // ------------------------------------------------- compile-time twiddles
 constexpr double kPiD = 3.14159265358979323846;
@@ -235,25 +235,93 @@ __device__ __forceinline__ float2 lds_tw(const float2* tw, int e) {
   return INV ? w : make_float2(w.x, -w.y);
 }
 
-// Line FFT, decimation in time.  In: lane q holds x[q + 4 p] in a[p].
-// Out: lane q holds X[R * brev2(q) + k] in a[k].
-template <int n, bool INV>
-__device__ __forceinline__ void line_dit(float2 (&a)[n / kQ], int q, const float2* tw) {
-  constexpr int R = n / kQ;
-  fft_reg<R, INV>(a);
-#pragma unroll
-  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], lds_tw<INV>(tw, q * k));
-  xlane_nat2brev<INV>(a, q);
+// --------------------------------------------- cross-lane radix-8 (Q = 8)
+// The 8 lanes of a line are relabelled ql = q (q < 4), 11 - q (q >= 4), so
+// that the partner at logical distance 4 is the DPP row_half_mirror partner
+// (lane i <-> 7 - i), while logical distances 2 and 1 stay the quad
+// permutes xor 2 and xor 1.
+constexpr int kMirror8 = 0x141;
+template <int Q>
+__device__ __forceinline__ int lane_log(int q) {
+  if constexpr (Q == 4) return q;
+  return q < 4 ? q : 11 - q;
 }
-// Line FFT, decimation in frequency.  In: lane q holds x[R * brev2(q) + m]
-// in a[m].  Out: lane q holds X[q + 4 k] in a[k].
-template <int n, bool INV>
-__device__ __forceinline__ void line_dif(float2 (&a)[n / kQ], int q, const float2* tw) {
-  constexpr int R = n / kQ;
-  xlane_brev2nat<INV>(a, q);
+template <int Q>
+__device__ __forceinline__ int brevq(int ql) {
+  if constexpr (Q == 4) return ((ql & 1) << 1) | ((ql >> 1) & 1);
+  return ((ql & 1) << 2) | (ql & 2) | ((ql >> 2) & 1);
+}
+// W_8^j, j = 0..3 (INV: exp(+2 pi i j / 8), else exp(-2 pi i j / 8))
+template <bool INV>
+__device__ __forceinline__ float2 w8(int j) {
+  constexpr float h = 0.707106781186547524401f;
+  const float c = j == 0 ? 1.0f : (j == 1 ? h : (j == 2 ? 0.0f : -h));
+  const float sn = j == 0 ? 0.0f : (j == 1 ? h : (j == 2 ? 1.0f : h));
+  return make_float2(c, INV ? sn : -sn);
+}
+// 8-point DFT across the lanes of a line, decimation in frequency: input
+// natural (logical lane ql holds x_ql), output bit-reversed (X_{brev3(ql)}).
+template <bool INV, int R>
+__device__ __forceinline__ void xlane8_nat2brev(float2 (&a)[R], int ql) {
+  const float s4 = (ql & 4) ? -1.0f : 1.0f, s2 = (ql & 2) ? -1.0f : 1.0f,
+              s1 = (ql & 1) ? -1.0f : 1.0f;
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
 #pragma unroll
-  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], lds_tw<INV>(tw, q * m));
+  for (int i = 0; i < R; ++i) {
+    float2 v = cmul(xstage<kMirror8>(a[i], s4), t8);
+    v = w4_lane3<INV>(xstage<kXor2>(v, s2), is3);
+    a[i] = xstage<kXor1>(v, s1);
+  }
+}
+// decimation in time: input bit-reversed, output natural
+template <bool INV, int R>
+__device__ __forceinline__ void xlane8_brev2nat(float2 (&a)[R], int ql) {
+  const float s4 = (ql & 4) ? -1.0f : 1.0f, s2 = (ql & 2) ? -1.0f : 1.0f,
+              s1 = (ql & 1) ? -1.0f : 1.0f;
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    float2 v = w4_lane3<INV>(xstage<kXor1>(a[i], s1), is3);
+    v = cmul(xstage<kXor2>(v, s2), t8);
+    a[i] = xstage<kMirror8>(v, s4);
+  }
+}
+
+// Line FFT over Q lanes, decimation in time.  In: logical lane ql holds
+// x[ql + Q p] in a[p].  Out: it holds X[R * brevq(ql) + k] in a[k].
+template <int n, bool INV, int Q = kQ>
+__device__ __forceinline__ void line_dit(float2 (&a)[n / Q], int ql, const float2* tw) {
+  constexpr int R = n / Q;
   fft_reg<R, INV>(a);
+#pragma unroll
+  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], lds_tw<INV>(tw, ql * k));
+  if constexpr (Q == 4)
+    xlane_nat2brev<INV>(a, ql);
+  else
+    xlane8_nat2brev<INV>(a, ql);
+}
+// Line FFT over Q lanes, decimation in frequency.  In: logical lane ql holds
+// x[R * brevq(ql) + m] in a[m].  Out: it holds X[ql + Q k] in a[k].
+template <int n, bool INV, int Q = kQ>
+__device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float2* tw) {
+  constexpr int R = n / Q;
+  if constexpr (Q == 4)
+    xlane_brev2nat<INV>(a, ql);
+  else
+    xlane8_brev2nat<INV>(a, ql);
+#pragma unroll
+  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], lds_tw<INV>(tw, ql * m));
+  fft_reg<R, INV>(a);
+}
+
+// A copy of v the compiler cannot see through: each phase then reads its own
+// twiddles from LDS instead of keeping one set live in registers across the
+// whole kernel.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
 // Barrier that orders LDS only, so global loads in flight (the intensity
@@ -309,33 +377,33 @@ __device__ __forceinline__ float wave_max(float v) {
 // Thread (c, q) with c < nd: support column kx = kx0 + c, rows ky = q + 4p.
 // Sw / Pw: buffer views of the LED's spectrum window and of the pupil.
 // Returns the partial max |P|^2 of this thread's support pixels.
-template <int n>
+template <int n, int Q = kQ>
 __device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_buffer_rsrc_t Pw,
                                             int N, int kx, int2 ch, int q, float scale,
-                                            float2 (&a)[n / kQ]) {
-  constexpr int R = n / kQ;
+                                            float2 (&a)[n / Q]) {
+  constexpr int R = n / Q;
   float pm = 0.0f;
   const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
-    const int ky = q + kQ * p;
+    const int ky = q + Q * p;
     const bool in = ky >= ch.x && ky <= ch.y;
-    const float2 xs = bload2(Sw, in ? s0 + p * (kQ * 8) * N : kOob);
-    const float2 pv = bload2(Pw, in ? p0 + p * (kQ * 8 * n) : kOob);
+    const float2 xs = bload2(Sw, in ? s0 + p * (Q * 8) * N : kOob);
+    const float2 pv = bload2(Pw, in ? p0 + p * (Q * 8 * n) : kOob);
     pm = fmaxf(pm, cabs2(pv));
     a[p] = cscale(cmul(pv, xs), scale);
   }
   return pm;
 }
 
-// phase B input: lane q of row y takes kx = q + 4p from T[kx - kx0][y]
-template <int n, int PAD = 16>
+// phase B input: logical lane q of row y takes kx = q + Q p from T[kx - kx0][y]
+template <int n, int PAD = 16, int Q = kQ>
 __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, int y, int q,
-                                          float2 (&a)[n / kQ]) {
-  constexpr int R = n / kQ;
+                                          float2 (&a)[n / Q]) {
+  constexpr int R = n / Q;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
-    const int c = q + kQ * p - kx0;
+    const int c = q + Q * p - kx0;
     a[p] = (c >= 0 && c < nd) ? buf[c * pitch<n, PAD>() + y] : make_float2(0.0f, 0.0f);
   }
 }
@@ -372,27 +440,27 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 }
 
 // Spectrum (and pupil) update of one support column kx: a[k] = Phi'(ky =
-// q + 4k, kx).  S_stored += conj(P) D / (max|P|^2 sigma); the pupil step
+// q + Q k, kx), q the logical lane.  S_stored += conj(P) D / (max|P|^2 sigma); the pupil step
 // conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
 // goes to P (mode 1) or to the increment slot (mode 2).
-template <int n>
-__device__ __forceinline__ void update_column(const float2 (&a)[n / kQ],
+template <int n, int Q = kQ>
+__device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Sw,
                                               __amdgpu_buffer_rsrc_t Pw,
                                               __amdgpu_buffer_rsrc_t Dw, int N, int kx, int2 ch,
                                               int q, float sigf, float pmax2, float smax,
                                               int mode) {
-  constexpr int R = n / kQ;
+  constexpr int R = n / Q;
   const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
   const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
   const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
   const bool upd_s = pmax2 > 0.0f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int ky = q + kQ * k;
+    const int ky = q + Q * k;
     const bool in = ky >= ch.x && ky <= ch.y;
-    const int offS = in ? s0 + k * (kQ * 8) * N : kOob;
-    const int offP = in ? p0 + k * (kQ * 8 * n) : kOob;
+    const int offS = in ? s0 + k * (Q * 8) * N : kOob;
+    const int offP = in ? p0 + k * (Q * 8 * n) : kOob;
     const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
     const float2 pv = bload2(Pw, offP);
     const float2 phi = cscale(cmul(pv, xs), sigf);
@@ -413,11 +481,13 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / kQ],
 // ===================================================== the update kernel
 // t.mode: 0 = spectrum only, 1 = pupil updated in place (one LED per tile in
 // the launch), 2 = pupil increment written to dP[slot] (LED groups).
-template <int n, int PAD>
-__global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restrict__ tiles,
-                                                        const Item* __restrict__ items) {
-  constexpr int R = n / kQ;
-  constexpr int NT = n * kQ;
+// Q lanes per line: 4 (R = n/4 points per lane) or 8 (R = n/8, twice the
+// waves per update); PAD and Q are the autotuner's choices.
+template <int n, int PAD, int Q>
+__global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict__ tiles,
+                                                       const Item* __restrict__ items) {
+  constexpr int R = n / Q;
+  constexpr int NT = n * Q;
   constexpr int NW = NT / 64;
   extern __shared__ float2 sbuf[];  // [nd][pitch]
   __shared__ float2 tw[n];
@@ -428,7 +498,7 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   const TileDev t = tiles[it.tile];
   const int mode = t.mode;
   const int tid = threadIdx.x;
-  const int q = tid & 3, line = tid >> 2;
+  const int q = lane_log<Q>(tid % Q), line = tid / Q;
   const int wave = tid >> 6;
   const int N = t.N;
 
@@ -444,8 +514,8 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
 
   // prefetch this thread's intensities for the modulus step: row `line`,
-  // columns [R*brev2(q), +R)
-  const int xc = R * brev2(q);
+  // columns [R*brevq(q), +R)
+  const int xc = R * brevq<Q>(q);
   float ipre[R];
 #pragma unroll
   for (int v = 0; v < R / 4; ++v) {
@@ -466,9 +536,9 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
 
   // ---- phase A: support columns, IFFT along ky
   if (col_line) {
-    pm = gather_phi<n>(Sw, Pw, N, kx, ch, q, sigf / (float)(n * n), a);
-    line_dit<n, true>(a, q, tw);
-    float2* dst = sbuf + line * pitch<n, PAD>() + R * brev2(q);
+    pm = gather_phi<n, Q>(Sw, Pw, N, kx, ch, q, sigf / (float)(n * n), a);
+    line_dit<n, true, Q>(a, opaque(q), tw);
+    float2* dst = sbuf + line * pitch<n, PAD>() + xc;
 #pragma unroll
     for (int k = 0; k < R; ++k) dst[k] = a[k];
   }
@@ -477,9 +547,9 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
   lds_barrier();
 
   // ---- phase B: rows, IFFT along kx
-  load_rows<n, PAD>(sbuf, t.kx0, t.nd, line, q, a);
+  load_rows<n, PAD, Q>(sbuf, t.kx0, t.nd, line, q, a);
   lds_barrier();  // T fully consumed; the buffer is reused below
-  line_dit<n, true>(a, q, tw);
+  line_dit<n, true, Q>(a, opaque(q), tw);
 
   // ---- modulus constraint + residual partials (row `line`, x = xc + k)
   float e_acc = 0.0f, i_acc = 0.0f;
@@ -492,28 +562,28 @@ __global__ __launch_bounds__(n * kQ) void update_kernel(const TileDev* __restric
     }
   }
 
-  // ---- phase B': FFT along x (lane q holds x-chunk brev2(q))
-  line_dif<n, false>(a, q, tw);
-  // a[k] = row-transform at kx = q + 4k; keep the support columns only
+  // ---- phase B': FFT along x (lane q holds x-chunk brevq(q))
+  line_dif<n, false, Q>(a, opaque(q), tw);
+  // a[k] = row-transform at kx = q + Q k; keep the support columns only
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int c = q + kQ * k - t.kx0;
+    const int c = q + Q * k - t.kx0;
     if (c >= 0 && c < t.nd) sbuf[c * pitch<n, PAD>() + line] = a[k];
   }
   lds_barrier();
 
   // ---- phase A': support columns, FFT along y, then the update
   if (col_line) {
-    const float2* srcp = sbuf + line * pitch<n, PAD>() + R * brev2(q);
+    const float2* srcp = sbuf + line * pitch<n, PAD>() + xc;
 #pragma unroll
     for (int m = 0; m < R; ++m) a[m] = srcp[m];
-    line_dif<n, false>(a, q, tw);
-    // a[k] = Phi'(ky = q + 4k, kx)
+    line_dif<n, false, Q>(a, opaque(q), tw);
+    // a[k] = Phi'(ky = q + Q k, kx)
     float pmax2 = red_pmax[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
     const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
-    update_column<n>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode);
+    update_column<n, Q>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode);
   }
 
   if (tid == 0) {
@@ -554,7 +624,7 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
     const int kx = t.kx0 + line;
     gather_phi<n>(Sw, Pw, t.N, kx, t.chord[kx], q, 1.0f / (float)(n * n), a);
     line_dit<n, true>(a, q, tw);
-    float2* dst = sbuf + line * pitch<n>() + R * brev2(q);
+    float2* dst = sbuf + line * pitch<n>() + R * brevq<kQ>(q);
 #pragma unroll
     for (int k = 0; k < R; ++k) dst[k] = a[k];
   }
@@ -562,7 +632,7 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
   load_rows<n>(sbuf, t.kx0, t.nd, line, q, a);
   line_dit<n, true>(a, q, tw);
   float4* dst = reinterpret_cast<float4*>(out + out_off[it.tile] + (size_t)it.led * n * n +
-                                          (size_t)line * n + R * brev2(q));
+                                          (size_t)line * n + R * brevq<kQ>(q));
 #pragma unroll
   for (int v = 0; v < R / 4; ++v)
     dst[v] = make_float4(cabs2(a[4 * v]), cabs2(a[4 * v + 1]), cabs2(a[4 * v + 2]),
@@ -571,7 +641,7 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 
 // ============================== sides whose transposes exceed LDS (n = 256)
 // Persistent form of the update: 512 threads run the lines of each phase in
-// 4n/512 rounds (R = n/4 points per thread, as above), the two transposes go
+// Q n/512 rounds (Q = 8 lanes per line, R = n/8 points per lane), the two transposes go
 // through this workgroup's own slot of global scratch ([nd][n] complex, the
 // same layout as the LDS buffer), and each workgroup loops over items
 // blockIdx.x, blockIdx.x + gridDim.x, ...  Phase B writes the support
@@ -580,28 +650,33 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 // input is overwritten.
 constexpr int kBigThreads = 512;
 
-template <int n>
+template <int n, int Q = 8>
 __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
                                                                  const Item* __restrict__ items,
                                                                  int count,
                                                                  float2* __restrict__ scratch) {
-  constexpr int R = n / kQ;
+  constexpr int R = n / Q;
   constexpr int NT = kBigThreads;
-  constexpr int LPR = NT / kQ;       // lines per round
+  constexpr int LPR = NT / Q;        // lines per round
   constexpr int ROUNDS = n / LPR;
   constexpr int NW = NT / 64;
   __shared__ float2 tw[n];
   __shared__ float red_pmax[NW];
   __shared__ double red_e[NW], red_i[NW];
-  const int tid = threadIdx.x;
-  const int q = tid & 3, l0 = tid >> 2;
-  const int wave = tid >> 6;
-  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  const int tid0 = threadIdx.x;
+  for (int e = tid0; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
   float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
-  const int xc = R * brev2(q);
   __syncthreads();
 
   for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+    // lane indices are re-derived per item through an opaque copy, so the
+    // compiler does not hoist every address they feed out of the item loop
+    // (that kept hundreds of values live across the whole kernel)
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int q_item = lane_log<Q>(tid % Q), l0 = tid / Q;
+    const int wave = tid >> 6;
+    const int xc = R * brevq<Q>(q_item);
     const Item it = items[ii];
     const TileDev t = tiles[it.tile];
     const int N = t.N;
@@ -618,10 +693,12 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
+      int q = q_item;  // opaque per round: keeps twiddle reads inside the round
+      asm volatile("" : "+v"(q));
       if (line < t.nd) {
         const int kx = t.kx0 + line;
-        pm = fmaxf(pm, gather_phi<n>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
-        line_dit<n, true>(a, q, tw);
+        pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
+        line_dit<n, true, Q>(a, q, tw);
         float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
 #pragma unroll
         for (int k = 0; k < R / 2; ++k)
@@ -637,8 +714,10 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
-      load_rows<n, 0>(sb, t.kx0, t.nd, line, q, a);
-      line_dit<n, true>(a, q, tw);
+      int q = q_item;  // opaque per round: keeps twiddle reads inside the round
+      asm volatile("" : "+v"(q));
+      load_rows<n, 0, Q>(sb, t.kx0, t.nd, line, q, a);
+      line_dit<n, true, Q>(a, q, tw);
       float iv[R];
 #pragma unroll
       for (int v = 0; v < R / 4; ++v) {
@@ -649,10 +728,10 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
         iv[4 * v + 3] = f.w;
       }
       modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
-      line_dif<n, false>(a, q, tw);
+      line_dif<n, false, Q>(a, q, tw);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int c = q + kQ * k - t.kx0;
+        const int c = q + Q * k - t.kx0;
         if (c >= 0 && c < t.nd) sb[(size_t)c * n + line] = a[k];
       }
     }
@@ -673,6 +752,8 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
+      int q = q_item;  // opaque per round: keeps twiddle reads inside the round
+      asm volatile("" : "+v"(q));
       if (line < t.nd) {
         const float4* src = reinterpret_cast<const float4*>(sb + (size_t)line * n + xc);
 #pragma unroll
@@ -681,9 +762,9 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           a[2 * k] = make_float2(f.x, f.y);
           a[2 * k + 1] = make_float2(f.z, f.w);
         }
-        line_dif<n, false>(a, q, tw);
+        line_dif<n, false, Q>(a, q, tw);
         const int kx = t.kx0 + line;
-        update_column<n>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
+        update_column<n, Q>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
       }
     }
     if (tid == 0) {
@@ -700,24 +781,26 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 }
 
 // forward model for the same sides: phases A and B, |psi|^2 out
-template <int n>
+template <int n, int Q = 8>
 __global__ __launch_bounds__(kBigThreads) void forward_kernel_big(const TileDev* __restrict__ tiles,
                                                                   const Item* __restrict__ items,
                                                                   int count, float* __restrict__ out,
                                                                   const int64_t* __restrict__ out_off,
                                                                   float2* __restrict__ scratch) {
-  constexpr int R = n / kQ;
+  constexpr int R = n / Q;
   constexpr int NT = kBigThreads;
-  constexpr int LPR = NT / kQ;
+  constexpr int LPR = NT / Q;
   constexpr int ROUNDS = n / LPR;
   __shared__ float2 tw[n];
-  const int tid = threadIdx.x;
-  const int q = tid & 3, l0 = tid >> 2;
-  for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  const int tid0 = threadIdx.x;
+  for (int e = tid0; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
   float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
-  const int xc = R * brev2(q);
   __syncthreads();
   for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+    int tid = tid0;  // opaque per item, as in update_kernel_big
+    asm volatile("" : "+v"(tid));
+    const int q = lane_log<Q>(tid % Q), l0 = tid / Q;
+    const int xc = R * brevq<Q>(q);
     const Item it = items[ii];
     const TileDev t = tiles[it.tile];
     const size_t woff = (size_t)it.wy0 * t.N + it.wx0;
@@ -730,8 +813,8 @@ __global__ __launch_bounds__(kBigThreads) void forward_kernel_big(const TileDev*
       const int line = l0 + LPR * rd;
       if (line < t.nd) {
         const int kx = t.kx0 + line;
-        gather_phi<n>(Sw, Pw, t.N, kx, t.chord[kx], q, 1.0f / (float)(n * n), a);
-        line_dit<n, true>(a, q, tw);
+        gather_phi<n, Q>(Sw, Pw, t.N, kx, t.chord[kx], q, 1.0f / (float)(n * n), a);
+        line_dit<n, true, Q>(a, q, tw);
         float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
 #pragma unroll
         for (int k = 0; k < R / 2; ++k)
@@ -742,8 +825,8 @@ __global__ __launch_bounds__(kBigThreads) void forward_kernel_big(const TileDev*
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
-      load_rows<n, 0>(sb, t.kx0, t.nd, line, q, a);
-      line_dit<n, true>(a, q, tw);
+      load_rows<n, 0, Q>(sb, t.kx0, t.nd, line, q, a);
+      line_dit<n, true, Q>(a, q, tw);
       float4* dst = reinterpret_cast<float4*>(out + out_off[it.tile] + (size_t)it.led * n * n +
                                               (size_t)line * n + xc);
 #pragma unroll
@@ -1029,21 +1112,23 @@ template <int n, int PAD = 16>
 size_t update_lds(int nd_max) {
   return (size_t)nd_max * pitch<n, PAD>() * sizeof(float2);
 }
-template <int n, int PAD>
+template <int n, int PAD, int Q>
 hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, int nd_max,
                             hipStream_t st) {
   const size_t lds = update_lds<n, PAD>(nd_max);
-  hipLaunchKernelGGL((update_kernel<n, PAD>), dim3(count), dim3(n * kQ), lds, st, tiles, items);
+  hipLaunchKernelGGL((update_kernel<n, PAD, Q>), dim3(count), dim3(n * Q), lds, st, tiles, items);
   return hipGetLastError();
 }
 template <int n>
 hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
                            int variant, hipStream_t st) {
   switch (variant) {
-    case 0: return launch_update_np<n, 16>(tiles, items, count, nd_max, st);
-    case 1: return launch_update_np<n, 1>(tiles, items, count, nd_max, st);
-    case 2: return launch_update_np<n, 8>(tiles, items, count, nd_max, st);
-    case 3: return launch_update_np<n, 32>(tiles, items, count, nd_max, st);
+    case 0: return launch_update_np<n, 16, 4>(tiles, items, count, nd_max, st);
+    case 1: return launch_update_np<n, 1, 4>(tiles, items, count, nd_max, st);
+    case 2: return launch_update_np<n, 8, 4>(tiles, items, count, nd_max, st);
+    case 3: return launch_update_np<n, 32, 4>(tiles, items, count, nd_max, st);
+    case 4: return launch_update_np<n, 1, 8>(tiles, items, count, nd_max, st);
+    case 5: return launch_update_np<n, 16, 8>(tiles, items, count, nd_max, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1057,13 +1142,17 @@ hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, 
 }
 template <int n>
 void set_lds_limit_n(int big) {
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)forward_kernel<n>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);

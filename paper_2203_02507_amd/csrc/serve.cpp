@@ -302,6 +302,10 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
     Launch l{};
     l.kind = Launch::UPDATE;
     l.n = ranges[i].first.first;
+    // one update variant per size for the whole process: if no plan has tuned
+    // this size yet, the server fixes the default, so served and planned
+    // results stay bitwise equal
+    if (!update_variant_known(l.n)) set_update_variant(l.n, 0);
     l.prec = ranges[i].first.second;
     l.nd_max = nd_max[ranges[i].first].first;
     l.box_max = nd_max[ranges[i].first].second;

@@ -221,21 +221,35 @@ def test_uneven_batch_matches_oracle(fpm, orc):
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
-def test_update_variants_bitwise_identical(fpm, orc, monkeypatch):
-    """The autotuner's variants differ only in LDS row padding: every variant
-    must give the same bits."""
-    tds = fpm_synth.full_fov_tiles(only=[3, 200], iterations=2, schedule=1, pupil_update=1)
+@pytest.mark.parametrize("n", [64, 96, 128])
+def test_update_variants(fpm, orc, monkeypatch, n):
+    """The autotuner's variants: 4 or 8 lanes per line, LDS row padding.
+    Variants of one lane count differ only in padding and give the same bits;
+    the 8-lane form orders its floating-point steps differently and must meet
+    the same tolerance against the oracle."""
+    rng = np.random.default_rng(n)
     descs, Is = [], []
-    for td in tds:
-        _, _, I = orc.synthesize(td, z_range=20.0)
-        descs.append(td.desc)
+    for k in range(2):
+        d = fpm_synth.TileDesc(n=n, upsample=3, led_rows=9, led_cols=9, iterations=2, schedule=1,
+                               pupil_update=1, tile_x_um=float(rng.uniform(-1000, 1000)),
+                               tile_y_um=float(rng.uniform(-1000, 1000)),
+                               defocus_um=float(rng.uniform(-20, 20)))
+        _, _, I = orc.synthesize(fpm_synth.TileDraw(desc=d, rng=rng))
+        descs.append(d)
         Is.append(I)
-    ref = None
-    for v in range(4):
+    refs = [oracle_run(orc, d, I) for d, I in zip(descs, Is)]
+    first = {}
+    for v in range(6):
         monkeypatch.setenv("FPM_UPDATE_VARIANT", str(v))
         _, out = run_gpu(fpm, descs, Is)
-        if ref is None:
-            ref = out
+        fam = 4 if v < 4 else 8
+        if fam not in first:
+            first[fam] = out
+            for (o, _, r), (o_ref, _, r_ref) in zip(out, refs):
+                assert rel(o, o_ref) <= TOL_OBJ, v
+                assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), v
         else:
-            for a, b in zip(out, ref):
+            for a, b in zip(out, first[fam]):
                 assert all(np.array_equal(x, y) for x, y in zip(a, b)), v
+    for a, b in zip(first[4], first[8]):
+        assert rel(a[0], b[0]) < 1e-5
