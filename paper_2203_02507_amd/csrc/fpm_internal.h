@@ -59,7 +59,9 @@ struct TileDev {
 };
 
 struct Item {      // one (tile, LED) update
-  int tile, led, wy0, wx0, slot, pad;
+  int tile, led, wy0, wx0;
+  int slot;        // member index within the tile's group of this step
+  int gsize;       // members of that group
 };
 
 struct StepTile {  // a tile that ran a group in this step
@@ -78,8 +80,12 @@ constexpr int kUpdateVariants = 6;
 // ignored for n <= 128.
 constexpr int kBigSlots = 256;
 constexpr size_t big_scratch_bytes(int n) { return (size_t)kBigSlots * n * n * 8; }
+// ranges (n <= 128 only): group-sequential form, workgroup b runs the items
+// ranges[b].x .. + ranges[b].y - 1 in order (one tile's LED group, slot
+// order) and applies the group's pupil mean itself; no pupil_reduce launch.
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         int variant, float2* big_scratch, hipStream_t st);
+                         int variant, float2* big_scratch, hipStream_t st,
+                         const int2* ranges = nullptr, int nranges = 0);
 hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
                                float* out, const int64_t* out_off, int nd_max,
                                float2* big_scratch, hipStream_t st);

@@ -91,6 +91,14 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// products with the fused multiply-add placed explicitly (no contraction
+// left to the compiler)
+__device__ __forceinline__ float2 cmul_fma(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cmulc_fma(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
+}
 __device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
 
 // multiply by W_len^k (INV: exp(+2 pi i k/len), else exp(-2 pi i k/len));
@@ -316,6 +324,13 @@ __device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float
   fft_reg<R, INV>(a);
 }
 
+// P + acc / count with one fused multiply-add per component (the group
+// mean, written the same way wherever it is applied)
+__device__ __forceinline__ float2 pupil_mean_step(float2 p, float2 acc, int count) {
+  const float inv = 1.0f / (float)count;
+  return make_float2(fmaf(acc.x, inv, p.x), fmaf(acc.y, inv, p.y));
+}
+
 // A copy of v the compiler cannot see through: each phase then reads its own
 // twiddles from LDS instead of keeping one set live in registers across the
 // whole kernel.
@@ -443,13 +458,17 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 // q + Q k, kx), q the logical lane.  S_stored += conj(P) D / (max|P|^2 sigma); the pupil step
 // conj(sigma S_stored) D / (sigma^2 smax) = conj(S_stored) D / (sigma smax)
 // goes to P (mode 1) or to the increment slot (mode 2).
-template <int n, int Q = kQ>
+// SEQ (one workgroup runs every member of a tile's LED group in slot
+// order): the increments are summed in place in slot 0, and the last member
+// applies P <- P + sum / count -- the same operations in the same order as
+// pupil_reduce_kernel, so both forms give the same bits.
+template <int n, int Q = kQ, bool SEQ = false>
 __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Sw,
                                               __amdgpu_buffer_rsrc_t Pw,
                                               __amdgpu_buffer_rsrc_t Dw, int N, int kx, int2 ch,
                                               int q, float sigf, float pmax2, float smax,
-                                              int mode) {
+                                              int mode, int slot = 0, int count = 1) {
   constexpr int R = n / Q;
   const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
   const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
@@ -463,15 +482,31 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
     const int offP = in ? p0 + k * (Q * 8 * n) : kOob;
     const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
     const float2 pv = bload2(Pw, offP);
-    const float2 phi = cscale(cmul(pv, xs), sigf);
-    const float2 d = csub(a[k], phi);
-    bstore2(Sw, upd_s ? offS : kOob, cadd(xs, cscale(cmulc(d, pv), inv_ps)));
+    // explicit fused multiply-adds: every instantiation of this function
+    // rounds the update identically, whatever the compiler contracts elsewhere
+    const float2 px = cmul_fma(pv, xs);  // D = Phi' - sigma P X
+    const float2 d = make_float2(fmaf(-px.x, sigf, a[k].x), fmaf(-px.y, sigf, a[k].y));
+    const float2 ts = cmulc_fma(d, pv);
+    bstore2(Sw, upd_s ? offS : kOob,
+            make_float2(fmaf(ts.x, inv_ps, xs.x), fmaf(ts.y, inv_ps, xs.y)));
     if (mode != 0) {
-      const float2 dp = cscale(cmulc(d, xs), inv_ss);
-      if (mode == 1)
-        bstore2(Pw, offP, cadd(pv, dp));
-      else
-        bstore2(Dw, offP, dp);
+      const float2 tp = cmulc_fma(d, xs);
+      if (mode == 1) {
+        bstore2(Pw, offP, make_float2(fmaf(tp.x, inv_ss, pv.x), fmaf(tp.y, inv_ss, pv.y)));
+      } else {
+        // the increment is rounded before any sum, as when it is stored for
+        // the separate group-mean kernel
+        const float2 dp = make_float2(__fmul_rn(tp.x, inv_ss), __fmul_rn(tp.y, inv_ss));
+        if constexpr (SEQ) {
+          const float2 acc = slot == 0 ? dp : cadd(bload2(Dw, offP), dp);
+          if (slot == count - 1)
+            bstore2(Pw, offP, pupil_mean_step(pv, acc, count));
+          else
+            bstore2(Dw, offP, acc);
+        } else {
+          bstore2(Dw, offP, dp);
+        }
+      }
     }
   }
 }
@@ -483,9 +518,13 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
 // the launch), 2 = pupil increment written to dP[slot] (LED groups).
 // Q lanes per line: 4 (R = n/4 points per lane) or 8 (R = n/8, twice the
 // waves per update); PAD and Q are the autotuner's choices.
-template <int n, int PAD, int Q>
+// SEQ: workgroup b runs items ranges[b].x .. + ranges[b].y - 1 one after
+// another (the members of one tile's LED group, in slot order); otherwise
+// workgroup b runs item b.
+template <int n, int PAD, int Q, bool SEQ>
 __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict__ tiles,
-                                                       const Item* __restrict__ items) {
+                                                       const Item* __restrict__ items,
+                                                       const int2* __restrict__ ranges) {
   constexpr int R = n / Q;
   constexpr int NT = n * Q;
   constexpr int NW = NT / 64;
@@ -494,7 +533,10 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
   __shared__ float red_pmax[NW];
   __shared__ double red_e[NW], red_i[NW];
 
-  const Item it = items[blockIdx.x];
+  // the body of one item; the group-sequential form loops over its range,
+  // the other runs it once (a loop there, even of one trip, costs registers)
+  auto run_item = [&](const int ii) {
+  const Item it = items[ii];
   const TileDev t = tiles[it.tile];
   const int mode = t.mode;
   const int tid = threadIdx.x;
@@ -508,7 +550,7 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
   const __amdgpu_buffer_rsrc_t Sw = make_rsrc(t.S + woff, (unsigned)(((size_t)N * N - woff) * 8));
   const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
   const __amdgpu_buffer_rsrc_t Iw = make_rsrc(t.I + (size_t)it.led * n * n, n * n * 4);
-  const __amdgpu_buffer_rsrc_t Dw = make_rsrc(t.dP + (size_t)it.slot * n * n, n * n * 8);
+  const __amdgpu_buffer_rsrc_t Dw = make_rsrc(t.dP + (SEQ ? 0 : (size_t)it.slot * n * n), n * n * 8);
 
   // twiddle table W_n^e = exp(+2 pi i e/n), correctly rounded at compile time
   for (int e = tid; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
@@ -583,7 +625,8 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
 #pragma unroll
     for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
     const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
-    update_column<n, Q>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode);
+    update_column<n, Q, SEQ>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode, it.slot,
+                             it.gsize);
   }
 
   if (tid == 0) {
@@ -594,6 +637,16 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
     }
     t.e_part[it.led] = e;
     t.i_part[it.led] = s;
+  }
+  };
+  if constexpr (SEQ) {
+    const int2 rg = ranges[blockIdx.x];
+    for (int ii = rg.x; ii < rg.x + rg.y; ++ii) {
+      run_item(ii);
+      lds_barrier();  // LDS and reductions are reused by the next member
+    }
+  } else {
+    run_item((int)blockIdx.x);
   }
 }
 
@@ -851,12 +904,11 @@ __global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __rest
   const int n = t.n, nn = n * n;
   const int ky = t.kx0 + blockIdx.x;
   const int2 ch = t.chord[ky];
-  const float inv = 1.0f / (float)s.count;
   for (int kx = ch.x + (int)threadIdx.x; kx <= ch.y; kx += 128) {
     const int px = ky * n + kx;
     float2 acc = t.dP[px];
     for (int m = 1; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * nn + px]);
-    t.P[px] = cadd(t.P[px], cscale(acc, inv));
+    t.P[px] = pupil_mean_step(t.P[px], acc, s.count);
   }
 }
 
@@ -1114,21 +1166,27 @@ size_t update_lds(int nd_max) {
 }
 template <int n, int PAD, int Q>
 hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, int nd_max,
-                            hipStream_t st) {
+                            const int2* ranges, int nranges, hipStream_t st) {
   const size_t lds = update_lds<n, PAD>(nd_max);
-  hipLaunchKernelGGL((update_kernel<n, PAD, Q>), dim3(count), dim3(n * Q), lds, st, tiles, items);
+  if (ranges) {
+    hipLaunchKernelGGL((update_kernel<n, PAD, Q, true>), dim3(nranges), dim3(n * Q), lds, st,
+                       tiles, items, ranges);
+  } else {
+    hipLaunchKernelGGL((update_kernel<n, PAD, Q, false>), dim3(count), dim3(n * Q), lds, st,
+                       tiles, items, nullptr);
+  }
   return hipGetLastError();
 }
 template <int n>
 hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
-                           int variant, hipStream_t st) {
+                           int variant, const int2* ranges, int nranges, hipStream_t st) {
   switch (variant) {
-    case 0: return launch_update_np<n, 16, 4>(tiles, items, count, nd_max, st);
-    case 1: return launch_update_np<n, 1, 4>(tiles, items, count, nd_max, st);
-    case 2: return launch_update_np<n, 8, 4>(tiles, items, count, nd_max, st);
-    case 3: return launch_update_np<n, 32, 4>(tiles, items, count, nd_max, st);
-    case 4: return launch_update_np<n, 1, 8>(tiles, items, count, nd_max, st);
-    case 5: return launch_update_np<n, 16, 8>(tiles, items, count, nd_max, st);
+    case 0: return launch_update_np<n, 16, 4>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 1: return launch_update_np<n, 1, 4>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 2: return launch_update_np<n, 8, 4>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 3: return launch_update_np<n, 32, 4>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 4: return launch_update_np<n, 1, 8>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 5: return launch_update_np<n, 16, 8>(tiles, items, count, nd_max, ranges, nranges, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1142,17 +1200,29 @@ hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, 
 }
 template <int n>
 void set_lds_limit_n(int big) {
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 4>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 4, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 4>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 4, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8, 4>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 4, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32, 4>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 4, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 8>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8, 4, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8>,
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 8, 4, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32, 4, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 32, 4, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 8, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 1, 8, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)forward_kernel<n>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -1170,7 +1240,8 @@ void set_lds_limits() {
 }  // namespace
 
 hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int count, int nd_max,
-                         int variant, float2* big_scratch, hipStream_t st) {
+                         int variant, float2* big_scratch, hipStream_t st, const int2* ranges,
+                         int nranges) {
   if (count <= 0) return hipSuccess;
   set_lds_limits();
   if (n == 256) {
@@ -1181,9 +1252,10 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
     return hipGetLastError();
   }
   switch (n) {
-    case 64: return launch_update_n<64>(tiles, items, count, nd_max, variant, st);
-    case 96: return launch_update_n<96>(tiles, items, count, nd_max, variant, st);
-    case 128: return launch_update_n<128>(tiles, items, count, nd_max, variant, st);
+    case 64: return launch_update_n<64>(tiles, items, count, nd_max, variant, ranges, nranges, st);
+    case 96: return launch_update_n<96>(tiles, items, count, nd_max, variant, ranges, nranges, st);
+    case 128:
+      return launch_update_n<128>(tiles, items, count, nd_max, variant, ranges, nranges, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -55,11 +55,20 @@ bool update_variant_known(int n) {
 }
 
 hipError_t launch_update_class(const Launch& l, const TileDev* tiles, const Item* items,
-                               hipStream_t st) {
+                               hipStream_t st, const int2* ranges) {
   if (l.prec == FPM_PREC_FP32_FFT)
     return launch_update(l.n, tiles, items, l.count, l.nd_max, update_variant(l.n), l.big_scratch,
-                         st);
+                         st, l.roff >= 0 ? ranges + l.roff : nullptr, l.rcount);
   return launch_update_mfma(l.n, l.prec, tiles, items, l.count, l.box_max, l.tabE, l.tabF, st);
+}
+
+bool use_group_seq(int groups) {
+  // Opt-in: it removes the group-mean launch and its pupil-increment traffic,
+  // but a step then takes as long as its largest group (one workgroup per
+  // group), and group sizes differ between tiles; on the full field that
+  // costs more than the group-mean launch saves.
+  if (const char* v = std::getenv("FPM_GROUP_SEQ")) return std::atoi(v) != 0 && groups > 0;
+  return false;
 }
 
 // ------------------------------------------------------------- DevBuf
@@ -159,6 +168,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
 
   // ---- work lists
   std::vector<Item> items;
+  std::vector<int2> ranges;
   std::vector<StepTile> steptiles;
   std::vector<int> ids;
   launches.clear();
@@ -229,6 +239,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
       continue;
     }
     for (int s = 0; s < max_steps; ++s) {
+      std::vector<char> seq_done(T, 0);  // tiles whose group mean runs inside the update
       for (auto& kv : uclass) {
         Launch l{};
         l.kind = Launch::UPDATE;
@@ -253,10 +264,27 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
             it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
             it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
             it.slot = m - tp.step_beg[s];
+            it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
             items.push_back(it);
           }
         }
         l.count = (int)items.size() - l.off;
+        if (l.count > 0 && l.prec == FPM_PREC_FP32_FFT && l.n <= 128) {
+          // items of one tile are contiguous and in slot order
+          std::vector<int2> rg;
+          for (int i = l.off; i < l.off + l.count;) {
+            int j = i;
+            while (j < l.off + l.count && items[j].tile == items[i].tile) ++j;
+            rg.push_back(make_int2(i - l.off, j - i));
+            i = j;
+          }
+          if (use_group_seq((int)rg.size())) {
+            l.roff = (int)ranges.size();
+            l.rcount = (int)rg.size();
+            ranges.insert(ranges.end(), rg.begin(), rg.end());
+            for (const int2& r : rg) seq_done[items[l.off + r.x].tile] = 1;
+          }
+        }
         if (l.count > 0) launches.push_back(l);
       }
       // pupil means of the groups that ran in this step
@@ -266,7 +294,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
       int nmax = 0;
       for (int t : active) {
         const TilePlan& tp = tiles[t];
-        if (host_tiles[t].mode != 2 || s >= tp.nsteps) continue;
+        if (host_tiles[t].mode != 2 || s >= tp.nsteps || seq_done[t]) continue;
         steptiles.push_back(StepTile{t, tp.step_beg[s + 1] - tp.step_beg[s]});
         nmax = std::max(nmax, tp.n);
       }
@@ -298,6 +326,14 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   if (!items.empty() &&
       !hip_ok(hipMemcpy(items_d.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice),
               "hipMemcpy(items)", &st))
+    return st;
+  if (!hip_ok(ranges_d.alloc(std::max<size_t>(1, ranges.size()) * sizeof(int2)),
+              "hipMalloc(ranges)", &st))
+    return st;
+  if (!ranges.empty() &&
+      !hip_ok(hipMemcpy(ranges_d.p, ranges.data(), ranges.size() * sizeof(int2),
+                        hipMemcpyHostToDevice),
+              "hipMemcpy(ranges)", &st))
     return st;
   if (!hip_ok(steps_d.alloc(std::max<size_t>(1, steptiles.size()) * sizeof(StepTile)),
               "hipMalloc(steps)", &st))
@@ -507,7 +543,7 @@ hipError_t Executor::enqueue_sweep(hipStream_t s) {
         break;
       }
       case Launch::UPDATE:
-        e = launch_update_class(l, tab, it + l.off, s);
+        e = launch_update_class(l, tab, it + l.off, s, (const int2*)ranges_d.p);
         break;
       case Launch::REDUCE:
         e = launch_pupil_reduce(tab, stp + l.off, l.count, l.n, s);
@@ -543,10 +579,12 @@ hipError_t Executor::tune(hipStream_t s) {
     int best = 0;
     float best_ms = 1e30f;
     for (int v = 0; v < kUpdateVariants && e == hipSuccess; ++v) {
-      e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s);  // warm-up
+      const int2* rg = l.roff >= 0 ? (const int2*)ranges_d.p + l.roff : nullptr;
+      e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s, rg,
+                        l.rcount);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       for (int r = 0; r < 3 && e == hipSuccess; ++r)
-        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s);
+        e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s, rg, l.rcount);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -633,7 +671,7 @@ hipError_t Executor::enqueue_forward(const float2* obj_src, float* out, hipStrea
 }
 
 size_t Executor::device_bytes() const {
-  const DevBuf* all[] = {&state, &table, &items_d, &steps_d, &ids_d, &jobs_d, &i_off_d, &o_off_d,
+  const DevBuf* all[] = {&state, &table, &items_d, &ranges_d, &steps_d, &ids_d, &jobs_d, &i_off_d, &o_off_d,
                          &p_off_d, &r_off_d, &obj_stage, &fwd_P, &fwd_table, &fwd_items,
                          &I_stage, &res_stage, &pupil_stage, &big_scratch};
   size_t b = 0;

@@ -30,14 +30,19 @@ struct Launch {
   const uint16_t* tabE = nullptr;  // UPDATE, MFMA: DFT tables
   const uint16_t* tabF = nullptr;
   float2* big_scratch = nullptr;   // UPDATE, n = 256: transpose slots
+  int roff = -1, rcount = 0;       // UPDATE, group-sequential form: range list slice
   int off = 0, count = 0;  // range in the item / step-tile / tile-id lists
   int iter = 0;            // ITER_END
 };
 
 // Launch one update class: the FP32 FFT kernel (prec 0, autotuned variant)
 // or the MFMA DFT kernel (prec 1, 2).
+// `ranges`: device range list of the group-sequential launches (l.roff >= 0).
 hipError_t launch_update_class(const Launch& l, const TileDev* tiles, const Item* items,
-                               hipStream_t st);
+                               hipStream_t st, const int2* ranges = nullptr);
+// Group-sequential form for a launch with `groups` tile groups (one
+// workgroup per group, no group-mean launch): FPM_GROUP_SEQ=1 selects it.
+bool use_group_seq(int groups);
 
 // Process-wide choice of update-kernel variant per tile size (autotuned on
 // first use; FPM_UPDATE_VARIANT=k forces one).
@@ -58,7 +63,7 @@ struct Executor {
   int ntiles = 0;
   int64_t NN_max = 0;
   int64_t total_updates = 0;
-  DevBuf state, table, items_d, steps_d, ids_d, jobs_d;
+  DevBuf state, table, items_d, steps_d, ids_d, jobs_d, ranges_d;
   std::vector<TileDev> host_tiles;
   std::vector<Launch> launches;
   std::vector<LineLaunch> init_line_launches;

@@ -266,6 +266,7 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
       it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
       it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
       it.slot = m - tp.step_beg[s];
+      it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
       by_n[{tp.n, tp.d.precision}].push_back(it);
     }
     auto& mx = nd_max[{tp.n, tp.d.precision}];

@@ -253,3 +253,28 @@ def test_update_variants(fpm, orc, monkeypatch, n):
                 assert all(np.array_equal(x, y) for x, y in zip(a, b)), v
     for a, b in zip(first[4], first[8]):
         assert rel(a[0], b[0]) < 1e-5
+
+
+def test_group_sequential_form_bitwise(fpm, orc, monkeypatch):
+    """One workgroup per tile group (members in slot order, pupil mean applied
+    by the last member) gives the bits of the concurrent form with its
+    separate group-mean kernel, for every schedule and pupil mode."""
+    tds = fpm_synth.full_fov_tiles(only=[9, 70, 140], iterations=2, schedule=1, pupil_update=1)
+    descs, Is = [], []
+    for k, td in enumerate(tds):
+        _, _, I = orc.synthesize(td, z_range=20.0)
+        td.desc.schedule = (1, 0, 2)[k]
+        td.desc.pupil_update = (1, 1, 0)[k]
+        descs.append(td.desc)
+        Is.append(I)
+    out = {}
+    for seq in ("0", "1"):
+        monkeypatch.setenv("FPM_GROUP_SEQ", seq)
+        _, out[seq] = run_gpu(fpm, descs, Is)
+    diffs = [(t, k, float(np.abs(x - y).max()))
+             for t, (a, b) in enumerate(zip(out["0"], out["1"]))
+             for k, (x, y) in enumerate(zip(a, b)) if not np.array_equal(x, y)]
+    assert not diffs, diffs
+    for t, d in enumerate(descs):
+        o_ref, _, _ = oracle_run(orc, d, Is[t])
+        assert rel(out["1"][t][0], o_ref) <= TOL_OBJ
