@@ -142,9 +142,10 @@ def sample_errors(plan, obj, tiles, refs):
     return out
 
 
-def cpu_baseline(n_tiles: int = 8):
+def cpu_baseline(n_tiles: int = 16):
     """FP64 oracle on a bounded sample: the first `n_tiles` tiles of the
-    same workload, one iteration each, one tile per host thread."""
+    same workload, one iteration each, one tile per host thread (at most 16,
+    the host share of one GPU)."""
     from concurrent.futures import ThreadPoolExecutor
     import fpm_synth
     import oracle

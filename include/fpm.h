@@ -221,8 +221,11 @@ typedef struct {
 /* A request loop on its own host thread: requests are admitted while their
  * device footprint fits `hbm_budget_bytes` and fewer than `max_slots` run;
  * every admitted request keeps its spectrum and pupil resident; each
- * scheduler tick launches the next dependent step of every admitted request
- * together (continuous batching).  Errors: FPM_E_ARG, FPM_E_DEVICE. */
+ * scheduler tick runs one iteration of every admitted request, step s of all
+ * of them in the same launches (continuous batching), and requests join and
+ * leave between ticks.  A server that has run a 256-px request also holds
+ * 128 MiB of transpose scratch until it is destroyed.
+ * Errors: FPM_E_ARG, FPM_E_DEVICE. */
 fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t **out);
 void fpm_server_destroy(fpm_server_t *server);
 

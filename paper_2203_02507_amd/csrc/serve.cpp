@@ -3,9 +3,11 @@
 // Requests are single-tile reconstructions (Sec. 3.1: tiles are independent
 // problems).  A host thread admits waiting requests while their device
 // footprint fits the budget and a slot is free, keeps every admitted
-// request's spectrum and pupil resident, and on each tick launches the next
-// dependent step (one LED, or one LED group, Sec. 3.2) of every admitted
-// request in the same kernels.  Each request's arithmetic is independent of
+// request's spectrum and pupil resident, and on each tick runs one whole
+// iteration of every admitted request: its dependent steps (one LED, or one
+// LED group, Sec. 3.2) go to the stream in order, step s of all requests in
+// the same kernels, with one host synchronisation per tick; requests are
+// admitted and retired between ticks.  Each request's arithmetic is independent of
 // what it is batched with (one workgroup per update, per-tile reductions in
 // fixed order), so a result is bitwise the same alone and in a mix.
 #include <algorithm>
@@ -47,7 +49,7 @@ struct Request {
   float2* obj_stage = nullptr;
   float* I_copy = nullptr;
   // progress
-  int iter = 0, step = 0;
+  int iter = 0;  // completed iterations (a tick runs one)
   // results (host)
   std::vector<float2> obj, pupil;
   std::vector<double> residual;
@@ -248,97 +250,107 @@ hipError_t fpm_server_s::finish(Request* r) {
   return e;
 }
 
-// One scheduler tick: the next dependent step of every admitted request.
+// One scheduler tick: one whole iteration of every admitted request -- its
+// dependent LED-group steps enqueued in stream order (step s of every
+// request in one launch per (size, precision) class, then the group means
+// of step s), then the iteration ends -- and one host synchronisation.
 hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
-  std::map<std::pair<int, int>, std::vector<Item>> by_n;  // (n, precision) classes
-  std::map<std::pair<int, int>, std::pair<int, int>> nd_max;  // class -> max nd, max MFMA box
-  std::vector<StepTile> st;
-  std::vector<int> ends;
-  int n_max = 0;
+  struct ClassLaunch {
+    std::pair<int, int> cls;  // (n, precision)
+    size_t off, count;
+    int nd_max, box_max;
+  };
+  int max_steps = 0, n_max = 0;
   for (Request* r : batch) {
-    const TilePlan& tp = r->plan;
-    const int s = r->step;
-    for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
-      const int j = tp.step_leds[m];
-      Item it{};
-      it.tile = r->slot;
-      it.led = j;
-      it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
-      it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
-      it.slot = m - tp.step_beg[s];
-      it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
-      by_n[{tp.n, tp.d.precision}].push_back(it);
-    }
-    auto& mx = nd_max[{tp.n, tp.d.precision}];
-    mx.first = std::max(mx.first, tp.nd);
-    mx.second = std::max(mx.second, mfma_box(tp.kx0, tp.nd));
-    n_max = std::max(n_max, tp.n);
-    if (r->td.mode == 2) st.push_back(StepTile{r->slot, tp.step_beg[s + 1] - tp.step_beg[s]});
-    if (s + 1 == tp.nsteps) ends.push_back(r->slot);
+    max_steps = std::max(max_steps, r->plan.nsteps);
+    n_max = std::max(n_max, r->plan.n);
   }
-  size_t nitems = 0;
-  for (auto& kv : by_n) nitems += kv.second.size();
-  hipError_t e = items.alloc(std::max<size_t>(1, nitems) * sizeof(Item));
+  std::vector<Item> flat;
+  std::vector<StepTile> st;
+  std::vector<std::vector<ClassLaunch>> step_launches(max_steps);
+  std::vector<std::pair<size_t, size_t>> step_means(max_steps);  // StepTile range per step
+  for (int s = 0; s < max_steps; ++s) {
+    std::map<std::pair<int, int>, std::vector<Item>> by_cls;
+    std::map<std::pair<int, int>, std::pair<int, int>> mx;  // max nd, max MFMA box
+    const size_t st0 = st.size();
+    for (Request* r : batch) {
+      const TilePlan& tp = r->plan;
+      if (s >= tp.nsteps) continue;
+      const std::pair<int, int> cls{tp.n, tp.d.precision};
+      for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
+        const int j = tp.step_leds[m];
+        Item it{};
+        it.tile = r->slot;
+        it.led = j;
+        it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+        it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+        it.slot = m - tp.step_beg[s];
+        it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
+        by_cls[cls].push_back(it);
+      }
+      auto& x = mx[cls];
+      x.first = std::max(x.first, tp.nd);
+      x.second = std::max(x.second, mfma_box(tp.kx0, tp.nd));
+      if (r->td.mode == 2) st.push_back(StepTile{r->slot, tp.step_beg[s + 1] - tp.step_beg[s]});
+    }
+    step_means[s] = {st0, st.size() - st0};
+    for (auto& kv : by_cls) {
+      step_launches[s].push_back(
+          ClassLaunch{kv.first, flat.size(), kv.second.size(), mx[kv.first].first,
+                      mx[kv.first].second});
+      flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+    }
+  }
+  hipError_t e = items.alloc(std::max<size_t>(1, flat.size()) * sizeof(Item));
   if (e == hipSuccess) e = steps.alloc(std::max<size_t>(1, st.size()) * sizeof(StepTile));
   if (e != hipSuccess) return e;
-  std::vector<Item> flat;
-  flat.reserve(nitems);
-  std::vector<std::pair<std::pair<int, int>, size_t>> ranges;
-  for (auto& kv : by_n) {
-    ranges.emplace_back(kv.first, flat.size());
-    flat.insert(flat.end(), kv.second.begin(), kv.second.end());
-  }
   e = hipMemcpyAsync(items.p, flat.data(), flat.size() * sizeof(Item), hipMemcpyHostToDevice,
                      stream);
   if (e == hipSuccess && !st.empty())
     e = hipMemcpyAsync(steps.p, st.data(), st.size() * sizeof(StepTile), hipMemcpyHostToDevice,
                        stream);
-  if (e == hipSuccess && !ends.empty())
-    e = hipMemcpyAsync(ids.p, ends.data(), ends.size() * sizeof(int), hipMemcpyHostToDevice,
-                       stream);
   const TileDev* tab = (const TileDev*)table.p;
-  for (size_t i = 0; e == hipSuccess && i < ranges.size(); ++i) {
-    const size_t b = ranges[i].second;
-    const size_t cnt = (i + 1 < ranges.size() ? ranges[i + 1].second : flat.size()) - b;
-    Launch l{};
-    l.kind = Launch::UPDATE;
-    l.n = ranges[i].first.first;
-    // one update variant per size for the whole process: if no plan has tuned
-    // this size yet, the server fixes the default, so served and planned
-    // results stay bitwise equal
-    if (!update_variant_known(l.n)) set_update_variant(l.n, 0);
-    l.prec = ranges[i].first.second;
-    l.nd_max = nd_max[ranges[i].first].first;
-    l.box_max = nd_max[ranges[i].first].second;
-    l.count = (int)cnt;
-    if (l.prec != FPM_PREC_FP32_FFT) e = dft_tables(l.n, l.prec, &l.tabE, &l.tabF);
-    if (e == hipSuccess && l.n == 256) {
-      e = big_scratch.alloc(big_scratch_bytes(256));
-      l.big_scratch = (float2*)big_scratch.p;
+  for (int s = 0; s < max_steps && e == hipSuccess; ++s) {
+    for (const ClassLaunch& cl : step_launches[s]) {
+      if (e != hipSuccess) break;
+      Launch l{};
+      l.kind = Launch::UPDATE;
+      l.n = cl.cls.first;
+      l.prec = cl.cls.second;
+      // one update variant per size for the whole process: if no plan has
+      // tuned this size yet, the server fixes the default, so served and
+      // planned results stay bitwise equal
+      if (!update_variant_known(l.n)) set_update_variant(l.n, 0);
+      l.nd_max = cl.nd_max;
+      l.box_max = cl.box_max;
+      l.count = (int)cl.count;
+      if (l.prec != FPM_PREC_FP32_FFT) e = dft_tables(l.n, l.prec, &l.tabE, &l.tabF);
+      if (e == hipSuccess && l.n == 256) {
+        e = big_scratch.alloc(big_scratch_bytes(256));
+        l.big_scratch = (float2*)big_scratch.p;
+      }
+      if (e == hipSuccess) e = launch_update_class(l, tab, (const Item*)items.p + cl.off, stream);
     }
-    if (e == hipSuccess) e = launch_update_class(l, tab, (const Item*)items.p + b, stream);
+    if (e == hipSuccess && step_means[s].second > 0)
+      e = launch_pupil_reduce(tab, (const StepTile*)steps.p + step_means[s].first,
+                              (int)step_means[s].second, n_max, stream);
   }
-  if (e == hipSuccess && !st.empty())
-    e = launch_pupil_reduce(tab, (const StepTile*)steps.p, (int)st.size(), n_max, stream);
-  // iteration ends: residual + normalisation; spectrum max for the next iteration
-  if (e == hipSuccess && !ends.empty()) {
-    // every request ending an iteration in this tick is at its own iteration index;
-    // launch per distinct index (usually one)
+  // iteration ends (residual + normalisation) and the spectrum max for the
+  // next iteration, one launch per distinct iteration index
+  if (e == hipSuccess) {
     std::map<int, std::vector<int>> by_iter;
-    for (Request* r : batch)
-      if (r->step + 1 == r->plan.nsteps) by_iter[r->iter].push_back(r->slot);
-    size_t off = 0;
+    for (Request* r : batch) by_iter[r->iter].push_back(r->slot);
     std::vector<int> flat_ids;
     for (auto& kv : by_iter) flat_ids.insert(flat_ids.end(), kv.second.begin(), kv.second.end());
     e = hipMemcpyAsync(ids.p, flat_ids.data(), flat_ids.size() * sizeof(int),
                        hipMemcpyHostToDevice, stream);
+    size_t off = 0;
     for (auto& kv : by_iter) {
       if (e != hipSuccess) break;
       e = launch_iter_end(tab, (const int*)ids.p + off, (int)kv.second.size(), kv.first, stream);
       if (e == hipSuccess) {
         int nmax = 0;
-        for (Request* r : batch)
-          if (r->step + 1 == r->plan.nsteps) nmax = std::max(nmax, r->plan.N);
+        for (Request* r : batch) nmax = std::max(nmax, r->plan.N);
         e = launch_smax(tab, (const int*)ids.p + off, (int)kv.second.size(), nmax * nmax, stream);
       }
       off += kv.second.size();
@@ -347,7 +359,6 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   return e;
 }
-
 void fpm_server_s::run() {
   (void)hipSetDevice(device);
   while (true) {
@@ -416,12 +427,8 @@ void fpm_server_s::run() {
     }
     for (auto it = active.begin(); it != active.end();) {
       Request* r = *it;
-      r->stats.updates += r->plan.step_beg[r->step + 1] - r->plan.step_beg[r->step];
-      bool done = false;
-      if (++r->step == r->plan.nsteps) {
-        r->step = 0;
-        if (++r->iter == r->plan.d.iterations) done = true;
-      }
+      r->stats.updates += r->plan.L;  // a tick runs one whole iteration
+      const bool done = ++r->iter == r->plan.d.iterations;
       if (done) {
         const hipError_t fe = finish(r);
         bool finite = true;
