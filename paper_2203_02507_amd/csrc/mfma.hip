@@ -184,6 +184,9 @@ __device__ __forceinline__ void ld8(const float* p0, const float* p1, float (&v)
   v[7] = b.w;
 }
 
+// elements per thread per batch of the support-box loops
+constexpr int kFill = 8;
+
 // precision 2 transforms the modulus correction psi' - psi forward
 template <int PREC>
 constexpr bool kDelta = PREC == 2;
@@ -243,23 +246,37 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
     float* PhR = lds;
     float* PhI = lds + box * p1;
     float pm = 0.0f, fm = 0.0f;
-    for (int e = tid; e < box * box; e += NT) {
-      const int ar = (int)(((float)e + 0.5f) * rbox);
-      const int br = e - ar * box;
-      const int a = ub + ar, b = ub + br;
-      float2 v = make_float2(0.0f, 0.0f);
-      if (a < n && b < n) {
-        const int2 ch = chord[b];
-        if (a >= ch.x && a <= ch.y) {
-          const float2 x = Sw[(size_t)a * N + b];
-          const float2 p = Pp[a * n + b];
-          pm = fmaxf(pm, cabs2(p));
-          v = cscale(cmul(p, x), sig);
-          fm = fmaxf(fm, cabs2(v));
+    // batches of kFill elements per thread: every load of a batch is issued
+    // before the first is used (one wave per SIMD hides little latency)
+    for (int e0 = 0; e0 < box * box; e0 += kFill * NT) {
+      float2 xs[kFill], ps[kFill];
+      int off[kFill];
+#pragma unroll
+      for (int j = 0; j < kFill; ++j) {
+        const int e = e0 + j * NT + tid;
+        const int ar = (int)(((float)e + 0.5f) * rbox);
+        const int br = e - ar * box;
+        const int a = ub + ar, b = ub + br;
+        bool in = e < box * box && a < n && b < n;
+        if (in) {
+          const int2 ch = chord[b];
+          in = a >= ch.x && a <= ch.y;
         }
+        off[j] = in ? ar * p1 + br : -1 - (e < box * box ? ar * p1 + br : 0);
+        xs[j] = in ? Sw[(size_t)a * N + b] : make_float2(0.0f, 0.0f);
+        ps[j] = in ? Pp[a * n + b] : make_float2(0.0f, 0.0f);
       }
-      PhR[ar * p1 + br] = v.x;
-      PhI[ar * p1 + br] = v.y;
+#pragma unroll
+      for (int j = 0; j < kFill; ++j) {
+        const int e = e0 + j * NT + tid;
+        if (e >= box * box) continue;
+        pm = fmaxf(pm, cabs2(ps[j]));
+        const float2 v = cscale(cmul(ps[j], xs[j]), sig);
+        fm = fmaxf(fm, cabs2(v));
+        const int o = off[j] >= 0 ? off[j] : -1 - off[j];
+        PhR[o] = v.x;
+        PhI[o] = v.y;
+      }
     }
     pm = wave_max(pm);
     fm = wave_max(fm);
@@ -287,7 +304,9 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
   {
     const float* PhR = lds;
     const float* PhI = lds + box * p1;
-    for (int k = 0; k < nk; ++k) {
+#pragma unroll
+    for (int k = 0; k < 2 * MS; ++k) {
+      if (k >= nk) break;
       const Op<PREC> A =
           load_tab<PREC>(tabE, G::EPL, (size_t)(32 * w + c32) * G::EP + ub + 16 * k + 8 * h);
 #pragma unroll
@@ -301,7 +320,6 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
           cmac<PREC>(a1r[j], a1i[j], A, make_data<PREC>(re, im, s1));
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
   lds_barrier();  // Phi consumed; the space becomes the per-wave M1 regions
@@ -333,7 +351,9 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
     a2r[i] = f16v{};
     a2i[i] = f16v{};
   }
-  for (int k = 0; k < nk; ++k) {
+#pragma unroll
+  for (int k = 0; k < 2 * MS; ++k) {
+    if (k >= nk) break;
     const int o = c32 * p1 + 16 * k + 8 * h;
     float re[8], im[8];
     ld8(M1R + o, M1R + o + 4, re);
@@ -345,7 +365,6 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
           load_tab<PREC>(tabE, G::EPL, (size_t)(32 * i + c32) * G::EP + ub + 16 * k + 8 * h);
       cmac<PREC>(a2r[i], a2i[i], A, B);
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
 
   // ---- modulus projection and residual partials, psi' kept in a2
@@ -417,7 +436,6 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
         cmac<PREC>(a3r[j], a3i[j], A, B);
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   lds_barrier();  // every wave is done with its M1 region
 
@@ -480,7 +498,6 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
           cmac<PREC>(a4r[s], a4i[s], A, make_data<PREC>(re, im, s4));
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
   lds_barrier();  // V consumed
@@ -525,17 +542,32 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
     const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sig) : 0.0f;
     const float inv_ss = smax > 0.0f ? 1.0f / (smax * sig) : 0.0f;
     float2* __restrict__ Dp = t.dP + (size_t)it.slot * n * n;
-    for (int e = tid; e < box * box; e += NT) {
-      const int ar = (int)(((float)e + 0.5f) * rbox);
-      const int br = e - ar * box;
-      const int a = ub + ar, b = ub + br;
-      if (a >= n || b >= n) continue;
-      const int2 ch = chord[b];
-      if (a < ch.x || a > ch.y) continue;
+    for (int e0 = 0; e0 < box * box; e0 += kFill * NT) {
+      float2 xb[kFill], pb[kFill];
+      int ab[kFill], bb[kFill];
+#pragma unroll
+      for (int j = 0; j < kFill; ++j) {
+        const int e = e0 + j * NT + tid;
+        const int ar = (int)(((float)e + 0.5f) * rbox);
+        const int a = ub + ar, b = ub + (e - ar * box);
+        bool in = e < box * box && a < n && b < n;
+        if (in) {
+          const int2 ch = chord[b];
+          in = a >= ch.x && a <= ch.y;
+        }
+        ab[j] = in ? a : -1;
+        bb[j] = b;
+        xb[j] = in ? Sw[(size_t)a * N + b] : make_float2(0.0f, 0.0f);
+        pb[j] = in ? Pp[a * n + b] : make_float2(0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int j = 0; j < kFill; ++j) {
+      if (ab[j] < 0) continue;
+      const int a = ab[j], b = bb[j], ar = a - ub, br = b - ub;
       const size_t so = (size_t)a * N + b;
       const int po = a * n + b;
-      const float2 xs = Sw[so];
-      const float2 pv = Pp[po];
+      const float2 xs = xb[j];
+      const float2 pv = pb[j];
       const float2 phi = cscale(cmul(pv, xs), sig);
       const float2 d = kDelta<PREC> ? make_float2(QR[br * pp + ar], QI[br * pp + ar])
                                     : make_float2(QR[br * pp + ar] - phi.x, QI[br * pp + ar] - phi.y);
@@ -550,6 +582,7 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
           Pp[po] = make_float2(pv.x + dp.x, pv.y + dp.y);
         else
           Dp[po] = dp;
+      }
       }
     }
   }

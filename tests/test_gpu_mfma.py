@@ -13,6 +13,11 @@ pytestmark = pytest.mark.gpu
 TOL_MFMA = 1e-3
 TOL_FP32 = 1e-4
 PRECS = [fpm_synth.PREC_MFMA_BF16X3, fpm_synth.PREC_MFMA_FP16]
+# Residual histories: residual = sum(|psi| - sqrt I)^2 / sum I, and near
+# convergence |psi| - sqrt I is ~3 % of sqrt I, so a relative error eps in
+# |psi| moves the residual by ~2 eps / 0.03.  FP16 products carry eps ~ 3e-4
+# (-> ~2 %, bound 5 %); split BF16 ~1e-5 (bound 1 %).
+RES_RTOL = {fpm_synth.PREC_MFMA_BF16X3: 1e-2, fpm_synth.PREC_MFMA_FP16: 5e-2}
 
 
 def rel(a, b):
@@ -57,7 +62,7 @@ def test_single_tile_mfma_matches_oracle(fpm, orc, prec):
           f"pupil {rel(P, P_ref):.3e}")
     assert err <= TOL_MFMA
     assert rel(P, P_ref) <= TOL_MFMA
-    assert np.allclose(r, r_ref, rtol=1e-2, atol=1e-9)
+    assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -80,7 +85,7 @@ def test_full_field_tiles_mfma_match_oracle(fpm, orc, prec):
     for t, ((o, P, r), (o_ref, P_ref, r_ref)) in enumerate(zip(out, refs)):
         assert errs[t] <= TOL_MFMA, t
         assert rel(P, P_ref) <= TOL_MFMA, t
-        assert np.allclose(r, r_ref, rtol=1e-2, atol=1e-9), t
+        assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9), t
 
 
 def test_mixed_precisions_and_sizes_in_one_plan(fpm, orc):
