@@ -179,6 +179,43 @@ def pick_upsample(fpm, td):
     return False
 
 
+def single_tile_bench(fpm, reps: int = 5):
+    """One 64-px tile, 15x15 LEDs, 10 iterations (2,250 updates), LEDs in
+    ascending illumination NA: the latency of one reconstruction for the
+    sequential sweep (pupil recovery on and off) and for the pipelined
+    schedule (Sec. 3.2 Fig. 6b/d, level-scheduled over iterations; the same
+    bits as sequential), mean over `reps` runs."""
+    import numpy as np
+    import torch
+    import fpm_synth
+
+    out = {}
+    td = fpm_synth.single_tile_64()[0]
+    obj = fpm_synth.draw_object_and_defocus(td, None).astype(np.complex64)
+    for name, sched, pupil in (("sequential_pupil", 0, 1), ("sequential", 0, 0),
+                               ("pipelined", 3, 0), ("led_groups", 1, 0)):
+        d = fpm_synth.single_tile_64(schedule=sched, pupil_update=pupil)[0].desc
+        plan = fpm.Plan([d])
+        o = torch.from_numpy(obj.reshape(-1).view(np.float32)).cuda()
+        I = torch.empty(plan.total_intensity, dtype=torch.float32, device="cuda")
+        fpm.fpm_forward(plan, o, None, I, fpm.FPM_MEM_DEVICE)
+        ob, pu, re = fpm.device_buffers(plan)
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, ob, pu, re)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, ob, pu, re)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        info = plan.infos[0]
+        out[name] = {"ms": round(ms, 3), "dependent_launches": info.levels,
+                     "updates_per_s": round(info.L * info.iterations / (ms / 1e3), 1)}
+    out["pipelined_speedup_vs_sequential"] = round(out["sequential"]["ms"] / out["pipelined"]["ms"], 2)
+    return out
+
+
 def uneven_objects(tds, device):
     """Seeded objects of every tile (host threads), packed on the device."""
     from concurrent.futures import ThreadPoolExecutor
@@ -485,6 +522,9 @@ def main():
     for td in tds:
         td.desc.precision = 0
 
+    single = single_tile_bench(fpm)
+    log("single tile: " + json.dumps(single))
+
     uneven = None
     if args.uneven_tiles > 0:
         uneven = uneven_bench(fpm, args.uneven_tiles, steps=1, warmup=1)
@@ -522,6 +562,7 @@ def main():
         "cpu_baseline": cpu,
         "mfma": mfma,
         "rel_l2_vs_oracle": {"tiles": sample, **errs} if sample else None,
+        "single_tile": single,
         "uneven_batch": uneven,
         "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},

@@ -40,6 +40,7 @@ DESC_FIELDS = (
 SCHED_SEQUENTIAL = 0      # one LED at a time, ascending illumination NA
 SCHED_LED_GROUPS = 1      # non-overlapping LED groups run concurrently
 SCHED_GROUP_ORDER = 2     # one LED at a time, in the grouped sweep order
+SCHED_PIPELINED = 3       # sequential sweep, updates of all iterations level-scheduled
 
 PREC_FP32_FFT = 0
 PREC_MFMA_BF16X3 = 1

@@ -65,7 +65,16 @@ typedef enum {
   FPM_SCHED_LED_GROUPS = 1,  /* Sec. 3.2: members of a non-overlapping LED
                                 group run concurrently from the group-start
                                 state; the pupil takes their mean increment  */
-  FPM_SCHED_GROUP_ORDER = 2  /* one LED at a time, in the grouped order      */
+  FPM_SCHED_GROUP_ORDER = 2, /* one LED at a time, in the grouped order      */
+  FPM_SCHED_PIPELINED = 3    /* Sec. 3.2 Fig. 6b/d: the sequential NA-order
+                                sweep with its updates over all iterations
+                                level-scheduled -- an update runs once every
+                                earlier update whose spectrum window overlaps
+                                it has run, so iteration k+1 starts on the
+                                inner LEDs while iteration k finishes the outer
+                                ones.  Same result as SEQUENTIAL (bitwise);
+                                with pupil recovery every update depends on the
+                                previous one and the levels are the sequence. */
 } fpm_schedule;
 
 typedef enum { FPM_MEM_HOST = 0, FPM_MEM_DEVICE = 1 } fpm_mem;
@@ -115,6 +124,8 @@ typedef struct {
   int64_t object_offset;       /* complex offset of this tile's [N][N]       */
   int64_t pupil_offset;        /* complex offset of this tile's [n][n]       */
   int64_t residual_offset;     /* offset of this tile's [iterations] doubles */
+  int32_t levels;              /* dependent launches of the whole sweep      */
+  int32_t reserved;
 } fpm_tile_info;
 
 typedef struct fpm_plan_s fpm_plan_t;

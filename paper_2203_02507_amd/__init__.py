@@ -27,7 +27,7 @@ FPM_OK, FPM_PENDING = 0, 1
 FPM_E_ARG, FPM_E_GEOMETRY, FPM_E_NOMEM, FPM_E_DEVICE = -1, -2, -3, -4
 FPM_E_DIVERGED, FPM_E_CANCELLED, FPM_E_UNSUPPORTED = -5, -6, -7
 FPM_MEM_HOST, FPM_MEM_DEVICE = 0, 1
-FPM_SCHED_SEQUENTIAL, FPM_SCHED_LED_GROUPS, FPM_SCHED_GROUP_ORDER = 0, 1, 2
+FPM_SCHED_SEQUENTIAL, FPM_SCHED_LED_GROUPS, FPM_SCHED_GROUP_ORDER, FPM_SCHED_PIPELINED = 0, 1, 2, 3
 FPM_PREC_FP32_FFT, FPM_PREC_MFMA_BF16X3, FPM_PREC_MFMA_FP16 = 0, 1, 2
 
 STATUS_NAMES = {0: "FPM_OK", 1: "FPM_PENDING", -1: "FPM_E_ARG", -2: "FPM_E_GEOMETRY",
@@ -68,6 +68,7 @@ class TileInfoC(C.Structure):
         ("min_tie_distance", C.c_double),
         ("intensity_offset", C.c_int64), ("object_offset", C.c_int64),
         ("pupil_offset", C.c_int64), ("residual_offset", C.c_int64),
+        ("levels", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -194,6 +195,7 @@ class TileInfo:
     object_offset: int
     pupil_offset: int
     residual_offset: int
+    levels: int
 
 
 class Plan:
@@ -229,7 +231,8 @@ class Plan:
     def tile_info(self, t: int) -> TileInfo:
         info = TileInfoC()
         check(lib.fpm_plan_tile_info(self._h, t, C.byref(info)))
-        return TileInfo(**{k: getattr(info, k) for k, _ in TileInfoC._fields_})
+        return TileInfo(**{k: getattr(info, k) for k, _ in TileInfoC._fields_
+                           if k != "reserved"})
 
     def tables(self, t: int):
         L = self.infos[t].L

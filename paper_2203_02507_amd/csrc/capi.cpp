@@ -116,6 +116,8 @@ fpm_status fpm_plan_tile_info(const fpm_plan_t* plan, int32_t tile, fpm_tile_inf
   info->object_offset = tp.o_off;
   info->pupil_offset = tp.p_off;
   info->residual_offset = tp.r_off;
+  info->levels = tp.nlevels;
+  info->reserved = 0;
   return FPM_OK;
 }
 

@@ -33,6 +33,11 @@ struct TilePlan {
   // derived schedule: step s of an iteration updates LEDs steps[sbeg[s] .. sbeg[s+1])
   std::vector<int32_t> step_leds, step_beg;
   int nsteps = 0;
+  // the whole sweep as dependent launches ("levels"): level g updates the
+  // (iteration prog_iter[i], LED prog_led[i]) for i in [prog_beg[g],
+  // prog_beg[g+1]); iteration prog_end[g] (or -1) ends after level g
+  std::vector<int32_t> prog_led, prog_iter, prog_beg, prog_end;
+  int nlevels = 0;
   int64_t i_off = 0, o_off = 0, p_off = 0, r_off = 0;  // offsets in concatenated arrays
 };
 
@@ -45,8 +50,8 @@ struct TileDev {
   float2* P;          // [n][n]  pupil
   const float* I;     // [L][n][n] intensities
   float2* dP;         // [max_group][n][n] pupil increments of the current group
-  double* e_part;     // [L] residual numerator per LED, this iteration
-  double* i_part;     // [L] sum of I per LED, this iteration
+  double* e_part;     // residual numerator per (iteration, LED): [iter * e_stride + LED]
+  double* i_part;     // sum of I per (iteration, LED), same indexing
   double* sigma;      // [1] lazy spectrum scale
   unsigned* smax;     // [1] bits of max |S|^2 (stored scale) at iteration start
   const int2* chord;  // [n] (lo, hi) per support column
@@ -56,12 +61,14 @@ struct TileDev {
   int wy0_j0, wx0_j0;  // window of the initial spectrum (the centred window)
   int mode;            // 0 spectrum only, 1 pupil in place, 2 pupil increments to dP
   int iters;           // iterations of this tile
+  int e_stride;        // L (partials kept per iteration) or 0 (one iteration at a time)
 };
 
 struct Item {      // one (tile, LED) update
   int tile, led, wy0, wx0;
   int slot;        // member index within the tile's group of this step
   int gsize;       // members of that group
+  int iter;        // iteration the update belongs to
 };
 
 struct StepTile {  // a tile that ran a group in this step

@@ -635,8 +635,8 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
       e += red_e[w];
       s += red_i[w];
     }
-    t.e_part[it.led] = e;
-    t.i_part[it.led] = s;
+    t.e_part[(size_t)it.iter * t.e_stride + it.led] = e;
+    t.i_part[(size_t)it.iter * t.e_stride + it.led] = s;
   }
   };
   if constexpr (SEQ) {
@@ -826,8 +826,8 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
         e += red_e[w];
         s += red_i[w];
       }
-      t.e_part[it.led] = e;
-      t.i_part[it.led] = s;
+      t.e_part[(size_t)it.iter * t.e_stride + it.led] = e;
+      t.i_part[(size_t)it.iter * t.e_stride + it.led] = s;
     }
     __syncthreads();  // the slot and the reduction arrays are reused by the next item
   }
@@ -924,9 +924,10 @@ __global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict
   __shared__ double r0[256], r1[256];
   __shared__ double s_scale;
   double e = 0.0, s = 0.0;
+  const size_t e0 = (size_t)iter * t.e_stride;
   for (int j = tid; j < t.L; j += 256) {
-    e += t.e_part[j];
-    s += t.i_part[j];
+    e += t.e_part[e0 + j];
+    s += t.i_part[e0 + j];
   }
   r0[tid] = e;
   r1[tid] = s;

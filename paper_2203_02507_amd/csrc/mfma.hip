@@ -592,8 +592,8 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
       e += red_e[v];
       s += red_i[v];
     }
-    t.e_part[it.led] = e;
-    t.i_part[it.led] = s;
+    t.e_part[(size_t)it.iter * t.e_stride + it.led] = e;
+    t.i_part[(size_t)it.iter * t.e_stride + it.led] = s;
   }
 }
 

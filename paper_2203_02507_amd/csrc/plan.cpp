@@ -134,29 +134,23 @@ void build_order(TilePlan& tp) {
 // [a1, b1]) meets row u1 + dr (columns [a2, b2]) under a column shift dc iff
 // a2 - b1 <= dc <= b2 - a1; the stencil marks every such (dr, dc).
 // Groups: greedy first fit over the processing order.
-void build_groups(TilePlan& tp) {
-  const int n = tp.n, W = 2 * n - 1;
-  std::vector<int> rlo(n, n), rhi(n, -1);
-  for (int u = 0; u < n; ++u)
-    for (int v = 0; v < n; ++v)
-      if (tp.mask[(size_t)u * n + v]) {
-        rlo[u] = std::min(rlo[u], v);
-        rhi[u] = std::max(rhi[u], v);
-      }
-  std::vector<uint8_t> stencil((size_t)W * W, 0);
-  for (int dr = -(n - 1); dr <= n - 1; ++dr)
-    for (int u1 = 0; u1 < n; ++u1) {
-      const int u2 = u1 + dr;
-      if (u2 < 0 || u2 >= n || rhi[u1] < rlo[u1] || rhi[u2] < rlo[u2]) continue;
-      const int lo = rlo[u2] - rhi[u1], hi = rhi[u2] - rlo[u1];
-      for (int dc = lo; dc <= hi; ++dc) stencil[(size_t)(dr + n - 1) * W + (dc + n - 1)] = 1;
-    }
-  auto conflict = [&](int j, int k) {
-    // pixel of j at offset a equals pixel of k at offset b: a - b = off_k - off_j
-    const int dr = tp.off[2 * k] - tp.off[2 * j], dc = tp.off[2 * k + 1] - tp.off[2 * j + 1];
+// Conflict relation of two LEDs: their windows on the high-resolution grid
+// share a support pixel, i.e. the offset difference lies in D0 - D0 (Sec.
+// 3.2).  D0 - D0 as a (2n-1)^2 stencil built from the row intervals of D0.
+struct Conflicts {
+  int n = 0, W = 0;
+  std::vector<uint8_t> stencil;
+  const TilePlan* tp = nullptr;
+  bool operator()(int j, int k) const {
+    const int dr = tp->off[2 * k] - tp->off[2 * j], dc = tp->off[2 * k + 1] - tp->off[2 * j + 1];
     if (dr <= -n || dr >= n || dc <= -n || dc >= n) return false;
     return stencil[(size_t)(dr + n - 1) * W + (dc + n - 1)] != 0;
-  };
+  }
+};
+Conflicts make_conflicts(const TilePlan& tp);
+
+void build_groups(TilePlan& tp) {
+  const Conflicts conflict = make_conflicts(tp);
   std::vector<std::vector<int>> groups;
   tp.group_of.assign(tp.L, -1);
   for (int j : tp.order) {
@@ -187,6 +181,100 @@ void build_groups(TilePlan& tp) {
     tp.max_group = std::max(tp.max_group, (int)g.size());
   }
   tp.gstart.push_back((int)tp.sweep.size());
+}
+
+Conflicts make_conflicts(const TilePlan& tp) {
+  Conflicts c;
+  const int n = tp.n, W = 2 * n - 1;
+  c.n = n;
+  c.W = W;
+  c.tp = &tp;
+  std::vector<int> rlo(n, n), rhi(n, -1);
+  for (int u = 0; u < n; ++u)
+    for (int v = 0; v < n; ++v)
+      if (tp.mask[(size_t)u * n + v]) {
+        rlo[u] = std::min(rlo[u], v);
+        rhi[u] = std::max(rhi[u], v);
+      }
+  c.stencil.assign((size_t)W * W, 0);
+  // pixel of j at window offset a equals pixel of k at offset b: a - b = off_k - off_j
+  for (int dr = -(n - 1); dr <= n - 1; ++dr)
+    for (int u1 = 0; u1 < n; ++u1) {
+      const int u2 = u1 + dr;
+      if (u2 < 0 || u2 >= n || rhi[u1] < rlo[u1] || rhi[u2] < rlo[u2]) continue;
+      const int lo = rlo[u2] - rhi[u1], hi = rhi[u2] - rlo[u1];
+      for (int dc = lo; dc <= hi; ++dc) c.stencil[(size_t)(dr + n - 1) * W + (dc + n - 1)] = 1;
+    }
+  return c;
+}
+
+// The whole sweep as levels of independent updates.  Iteration-aligned
+// schedules: level = one step of one iteration, the iteration ends after its
+// last step.  PIPELINED (Sec. 3.2 Fig. 6b/d): the updates (k, j) of the
+// sequential NA-order sweep, iterations unrolled, each at 1 + the highest
+// level of an earlier update it conflicts with (its own LED's previous
+// update included); with pupil recovery every update shares the pupil, so
+// each depends on the one before it.
+void build_program(TilePlan& tp) {
+  tp.prog_led.clear();
+  tp.prog_iter.clear();
+  tp.prog_beg.assign(1, 0);
+  tp.prog_end.clear();
+  const int K = tp.d.iterations;
+  if (tp.d.schedule != FPM_SCHED_PIPELINED) {
+    for (int k = 0; k < K; ++k)
+      for (int s = 0; s < tp.nsteps; ++s) {
+        for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
+          tp.prog_led.push_back(tp.step_leds[m]);
+          tp.prog_iter.push_back(k);
+        }
+        tp.prog_beg.push_back((int)tp.prog_led.size());
+        tp.prog_end.push_back(s + 1 == tp.nsteps ? k : -1);
+      }
+    tp.nlevels = (int)tp.prog_end.size();
+    return;
+  }
+  const Conflicts conflict = make_conflicts(tp);
+  std::vector<std::vector<int>> conf(tp.L);
+  for (int j = 0; j < tp.L; ++j)
+    for (int k = 0; k < tp.L; ++k)
+      if (conflict(j, k)) conf[j].push_back(k);
+  std::vector<int> last(tp.L, 0);  // level of each LED's latest update (0: none yet)
+  std::vector<int> lvl_of;         // level of update (k, position in order)
+  std::vector<int> iter_end(K, 0);
+  int top = 0;
+  for (int k = 0; k < K; ++k)
+    for (int j : tp.order) {
+      int lv = 0;
+      if (tp.d.pupil_update) {
+        lv = top + 1;
+      } else {
+        for (int c : conf[j]) lv = std::max(lv, last[c]);
+        lv += 1;
+      }
+      last[j] = lv;
+      top = std::max(top, lv);
+      iter_end[k] = std::max(iter_end[k], lv);
+      lvl_of.push_back(lv);
+    }
+  tp.nlevels = top;
+  // bucket the updates by level, in sweep order within a level
+  std::vector<int> count(top + 2, 0);
+  for (int lv : lvl_of) ++count[lv];
+  std::vector<int> start(top + 2, 0);
+  for (int g = 1; g <= top; ++g) start[g + 1] = start[g] + count[g];
+  tp.prog_led.assign(lvl_of.size(), 0);
+  tp.prog_iter.assign(lvl_of.size(), 0);
+  std::vector<int> fill(start);
+  for (size_t u = 0; u < lvl_of.size(); ++u) {
+    const int at = fill[lvl_of[u]]++;
+    tp.prog_led[at] = tp.order[u % tp.L];
+    tp.prog_iter[at] = (int)(u / tp.L);
+  }
+  tp.prog_beg.clear();
+  tp.prog_end.assign(top, -1);
+  for (int g = 1; g <= top + 1; ++g) tp.prog_beg.push_back(start[g]);
+  for (int k = 0; k < K; ++k) tp.prog_end[iter_end[k] - 1] = k;
 }
 
 void build_steps(TilePlan& tp) {
@@ -224,7 +312,7 @@ fpm_status build_tile_plan(const fpm_tile_desc& d, TilePlan& tp, std::string& er
   }
   if (d.upsample < 1 || d.upsample > 8 || d.led_rows < 1 || d.led_cols < 1 ||
       d.led_rows * d.led_cols > 4096 || d.iterations < 0 || d.iterations > 100000 ||
-      (d.pupil_update != 0 && d.pupil_update != 1) || d.schedule < 0 || d.schedule > 2 ||
+      (d.pupil_update != 0 && d.pupil_update != 1) || d.schedule < 0 || d.schedule > 3 ||
       d.precision < 0 || d.precision > 2) {
     err = "tile descriptor field out of range";
     return FPM_E_ARG;
@@ -258,6 +346,7 @@ fpm_status build_tile_plan(const fpm_tile_desc& d, TilePlan& tp, std::string& er
   build_groups(tp);
   build_pupil(tp);
   build_steps(tp);
+  build_program(tp);
   return FPM_OK;
 }
 

@@ -94,6 +94,7 @@ Executor::~Executor() {
 
 namespace {
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+bool piped(const TilePlan& tp) { return tp.d.schedule == FPM_SCHED_PIPELINED; }
 }  // namespace
 
 fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
@@ -117,8 +118,10 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     lay[t].S = take(NN * 8);
     lay[t].P = take(nn * 8);
     lay[t].dP = take((grouped ? tp.max_group : 1) * nn * 8);
-    lay[t].e = take((int64_t)tp.L * 8);
-    lay[t].i = take((int64_t)tp.L * 8);
+    // residual partials: per iteration for pipelined tiles (iterations overlap)
+    const int64_t eparts = (int64_t)tp.L * (piped(tp) ? std::max(1, tp.d.iterations) : 1);
+    lay[t].e = take(eparts * 8);
+    lay[t].i = take(eparts * 8);
     lay[t].sig = take(8);
     lay[t].smax = take(4);
     lay[t].chord = take((int64_t)tp.n * 8);
@@ -155,6 +158,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     d.wx0_j0 = tp.N / 2 - tp.n / 2;
     d.mode = !tp.d.pupil_update ? 0 : (tp.d.schedule == FPM_SCHED_LED_GROUPS ? 2 : 1);
     d.iters = tp.d.iterations;
+    d.e_stride = piped(tp) ? tp.L : 0;
     // static tables
     if (!hip_ok(hipMemcpy((void*)d.chord, tp.chord.data(), (size_t)tp.n * 8, hipMemcpyHostToDevice),
                 "hipMemcpy(chord)", &st))
@@ -219,7 +223,7 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   for (int k = 0; k < max_iter; ++k) {
     std::vector<int> active;
     for (int t = 0; t < T; ++t)
-      if (tiles[t].d.iterations > k) active.push_back(t);
+      if (tiles[t].d.iterations > k && !piped(tiles[t])) active.push_back(t);
     const int body_start = (int)launches.size();
     if (k > 0 && active == prev_active && reuse_from >= 0) {
       // identical work lists: replay the previous iteration's launches
@@ -302,10 +306,12 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
       r.n = nmax;
       if (r.count > 0) launches.push_back(r);
     }
-    Launch e = id_range(active);
-    e.kind = Launch::ITER_END;
-    e.iter = k;
-    launches.push_back(e);
+    if (!active.empty()) {
+      Launch e = id_range(active);
+      e.kind = Launch::ITER_END;
+      e.iter = k;
+      launches.push_back(e);
+    }
     std::vector<int> next;
     for (int t : active)
       if (tiles[t].d.iterations > k + 1) next.push_back(t);
@@ -316,6 +322,67 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     }
     reuse_from = body_start;
     prev_active = active;
+  }
+  // pipelined tiles: their level programs, level g of every such tile in one
+  // launch per (n, precision) class, iteration ends where a program has them
+  {
+    int max_levels = 0;
+    for (const TilePlan& tp : tiles)
+      if (piped(tp)) max_levels = std::max(max_levels, tp.nlevels);
+    for (int g = 0; g < max_levels; ++g) {
+      for (auto& kv : uclass) {
+        Launch l{};
+        l.kind = Launch::UPDATE;
+        l.n = kv.first.first;
+        l.prec = kv.first.second;
+        l.nd_max = kv.second.first;
+        l.box_max = kv.second.second;
+        if (l.n == 256) l.big_scratch = (float2*)big_scratch.p;
+        if (l.prec != FPM_PREC_FP32_FFT) {
+          l.tabE = utabs[kv.first].first;
+          l.tabF = utabs[kv.first].second;
+        }
+        l.off = (int)items.size();
+        for (int t = 0; t < T; ++t) {
+          const TilePlan& tp = tiles[t];
+          if (!piped(tp) || tp.n != l.n || tp.d.precision != l.prec || g >= tp.nlevels) continue;
+          const int b = tp.prog_beg[g], e = tp.prog_beg[g + 1];
+          for (int m = b; m < e; ++m) {
+            const int j = tp.prog_led[m];
+            Item it{};
+            it.tile = t;
+            it.led = j;
+            it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+            it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+            it.slot = m - b;
+            it.gsize = e - b;
+            it.iter = tp.prog_iter[m];
+            items.push_back(it);
+          }
+        }
+        l.count = (int)items.size() - l.off;
+        if (l.count > 0) launches.push_back(l);
+      }
+      std::map<int, std::vector<int>> ends;  // iteration -> tiles ending it after level g
+      for (int t = 0; t < T; ++t) {
+        const TilePlan& tp = tiles[t];
+        if (piped(tp) && g < tp.nlevels && tp.prog_end[g] >= 0) ends[tp.prog_end[g]].push_back(t);
+      }
+      for (auto& kv : ends) {
+        Launch e = id_range(kv.second);
+        e.kind = Launch::ITER_END;
+        e.iter = kv.first;
+        launches.push_back(e);
+        std::vector<int> next;
+        for (int t : kv.second)
+          if (tiles[t].d.iterations > kv.first + 1) next.push_back(t);
+        if (!next.empty()) {
+          Launch m = id_range(next);
+          m.kind = Launch::SMAX;
+          launches.push_back(m);
+        }
+      }
+    }
   }
   total_updates = 0;
   for (const TilePlan& tp : tiles) total_updates += (int64_t)tp.d.iterations * tp.L;

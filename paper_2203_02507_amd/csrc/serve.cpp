@@ -154,6 +154,7 @@ bool fpm_server_s::admit(Request* r, std::string& err) {
   d.wx0_j0 = tp.N / 2 - tp.n / 2;
   d.mode = !tp.d.pupil_update ? 0 : (grouped ? 2 : 1);
   d.iters = tp.d.iterations;
+  d.e_stride = 0;  // iterations run one at a time: one set of residual partials
   hipError_t e = hipSuccess;
   if (r->where == FPM_MEM_HOST)
     e = hipMemcpyAsync(r->I_copy, r->I_user, (size_t)tp.L * nn * 4, hipMemcpyHostToDevice, stream);

@@ -278,3 +278,35 @@ def test_group_sequential_form_bitwise(fpm, orc, monkeypatch):
     for t, d in enumerate(descs):
         o_ref, _, _ = oracle_run(orc, d, Is[t])
         assert rel(out["1"][t][0], o_ref) <= TOL_OBJ
+
+
+@pytest.mark.parametrize("pupil", [0, 1])
+def test_pipelined_equals_sequential_bitwise(fpm, orc, pupil):
+    """Sec. 3.2 Fig. 6b/d: the level-scheduled sweep over all iterations gives
+    the bits of the sequential NA-order sweep, in a plan that also holds tiles
+    of the other schedules; the sequential result is checked against the
+    oracle."""
+    tds = fpm_synth.full_fov_tiles(only=[12, 100, 190], iterations=3, schedule=0,
+                                   pupil_update=pupil)
+    descs, Is = [], []
+    for td in tds:
+        _, _, I = orc.synthesize(td, z_range=20.0)
+        descs.append(td.desc)
+        Is.append(I)
+    other = fpm_synth.TileDesc(n=64, upsample=4, led_rows=9, led_cols=9, iterations=2,
+                               schedule=1, pupil_update=1)
+    _, _, I_other = orc.synthesize(fpm_synth.TileDraw(desc=other, rng=np.random.default_rng(8)))
+    _, seq = run_gpu(fpm, descs + [other], Is + [I_other])
+    import copy
+    piped = [copy.copy(d) for d in descs]
+    for d in piped:
+        d.schedule = fpm_synth.SCHED_PIPELINED
+    plan, pip = run_gpu(fpm, piped + [other], Is + [I_other])
+    if pupil == 0:
+        assert all(i.levels < i.iterations * i.L for i in plan.infos[:3])
+    for a, b in zip(seq, pip):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for t, d in enumerate(descs):
+        o_ref, _, r_ref = oracle_run(orc, d, Is[t])
+        assert rel(pip[t][0], o_ref) <= TOL_OBJ
+        assert np.allclose(pip[t][2], r_ref, rtol=1e-4, atol=1e-9)

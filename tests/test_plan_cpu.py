@@ -171,3 +171,50 @@ def test_n256_plan_tables_and_precision(fpm, orc):
     with pytest.raises(fpm.FpmError) as e:
         fpm.Plan([d])
     assert e.value.status == fpm.FPM_E_UNSUPPORTED
+
+
+def _brute_levels(orc, d, pupil):
+    """Level count of the pipelined sweep from pixel coverage: two LEDs
+    conflict when some high-resolution pixel lies in both support windows."""
+    mask, _ = orc.support(d)
+    st, off = orc.offsets(d)
+    assert st == 0
+    n, N, L = d.n, d.N, d.led_rows * d.led_cols
+    uu, vv = np.nonzero(mask)
+    cover = {}
+    for j in range(L):
+        r0 = N // 2 + off[j, 0] - n // 2
+        c0 = N // 2 + off[j, 1] - n // 2
+        for p in ((r0 + uu) * N + (c0 + vv)).tolist():
+            cover.setdefault(p, []).append(j)
+    conf = [set([j]) for j in range(L)]
+    for leds in cover.values():
+        for a in leds:
+            conf[a].update(leds)
+    last = [0] * L
+    top = 0
+    for _ in range(d.iterations):
+        for j in orc.order(d):
+            lv = top + 1 if pupil else 1 + max(last[c] for c in conf[j])
+            last[j] = lv
+            top = max(top, lv)
+    return top
+
+
+def test_pipelined_levels_match_pixel_coverage(fpm, orc):
+    """Sec. 3.2 Fig. 6b/d: the level count of the pipelined sweep equals an
+    independent count from pixel coverage; with pupil recovery the levels are
+    the sequence; iteration-aligned schedules have iterations x steps levels."""
+    d = fpm_synth.single_tile_64(iterations=10, pupil_update=0)[0].desc
+    d.schedule = fpm_synth.SCHED_PIPELINED
+    info = fpm.Plan([d]).infos[0]
+    assert info.levels == _brute_levels(orc, d, pupil=False) == 474
+    assert info.steps == d.led_rows * d.led_cols
+    d.pupil_update = 1
+    assert fpm.Plan([d]).infos[0].levels == 10 * 225
+    t = fpm_synth.full_fov_tiles(only=[201], iterations=3, pupil_update=0)[0].desc
+    t.schedule = fpm_synth.SCHED_PIPELINED
+    assert fpm.Plan([t]).infos[0].levels == _brute_levels(orc, t, pupil=False)
+    t.schedule = fpm_synth.SCHED_LED_GROUPS
+    i = fpm.Plan([t]).infos[0]
+    assert i.levels == 3 * i.steps == 3 * i.ngroups
