@@ -194,6 +194,22 @@ fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem whe
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
 
+/* Stitch reconstructed tiles into one field of view (Sec. 3.1, Eq. (1)).
+ *   tiles  complex64 [rows][cols][side][side]: the tile objects on their grid,
+ *          row-major, neighbours sharing `overlap` pixels (stride
+ *          side - overlap along both axes).
+ *   out    complex64 [H][W], H = rows (side - overlap) + overlap, W likewise
+ *          with cols.
+ * Each row of tiles is merged left to right, then the merged rows top to
+ * bottom: f1 is kept up to the middle of the overlap (width - overlap/2),
+ * after it f2 scaled by mu1 / mu2, the complex means of the two images over
+ * their shared overlap strip (FP64); with overlap 0 the tiles are
+ * concatenated.  `where` applies to both buffers; the call returns once `out`
+ * is written.  Errors: FPM_E_ARG (NULL, rows or cols < 1, overlap outside
+ * [0, side/2]), FPM_E_NOMEM, FPM_E_DEVICE. */
+fpm_status fpm_stitch(const void *tiles, int32_t rows, int32_t cols, int32_t side,
+                      int32_t overlap, void *out, fpm_mem where, void *hip_stream);
+
 /* Per-kind kernel timing of one reconstruction (profiling aid). */
 typedef enum {
   FPM_KERNEL_UPDATE = 0,      /* fused LED-tile update (the hot loop)          */

@@ -38,7 +38,7 @@ STATUS_NAMES = {0: "FPM_OK", 1: "FPM_PENDING", -1: "FPM_E_ARG", -2: "FPM_E_GEOME
 EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_tables",
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
-           "fpm_last_error", "fpm_version", "fpm_profile_reconstruct")
+           "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch")
 
 
 class FpmError(RuntimeError):
@@ -119,6 +119,8 @@ def _load():
     L.fpm_cancel.restype = C.c_int
     L.fpm_profile_reconstruct.argtypes = [vp, vp, C.POINTER(KernelTimeC), vp]
     L.fpm_profile_reconstruct.restype = C.c_int
+    L.fpm_stitch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int, vp]
+    L.fpm_stitch.restype = C.c_int
     L.fpm_last_error.argtypes = []
     L.fpm_last_error.restype = C.c_char_p
     L.fpm_version.argtypes = []
@@ -274,6 +276,18 @@ def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:
                                       _stream(stream)))
     return {name: {"launches": out[i].launches, "items": out[i].items,
                    "total_ms": out[i].total_ms} for i, name in enumerate(KERNEL_KINDS)}
+
+
+def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where: int,
+               stream=None) -> int:
+    """Sec. 3.1 Eq. (1): tiles complex64 [rows][cols][side][side] -> out
+    complex64 [H][W] (see include/fpm.h)."""
+    return check(lib.fpm_stitch(_ptr(tiles, where), rows, cols, side, overlap, _ptr(out, where),
+                                where, _stream(stream)))
+
+
+def stitched_shape(rows: int, cols: int, side: int, overlap: int):
+    return rows * (side - overlap) + overlap, cols * (side - overlap) + overlap
 
 
 def version() -> str:

@@ -139,6 +139,45 @@ fpm_status fpm_plan_device_bytes(const fpm_plan_t* plan, size_t* bytes) {
   return FPM_OK;
 }
 
+fpm_status fpm_stitch(const void* tiles, int32_t rows, int32_t cols, int32_t side,
+                      int32_t overlap, void* out, fpm_mem where, void* hip_stream) {
+  if (!tiles || !out || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_stitch: NULL argument or bad memory kind");
+  if (rows < 1 || cols < 1 || side < 2 || side > 65536 || overlap < 0 || 2 * overlap > side ||
+      (int64_t)rows * cols > (1 << 20))
+    return fail(FPM_E_ARG, "fpm_stitch: grid, side or overlap out of range (0 <= overlap <= side/2)");
+  const int64_t W = (int64_t)cols * (side - overlap) + overlap;
+  const int64_t H = (int64_t)rows * (side - overlap) + overlap;
+  if (W * H > ((int64_t)1 << 34)) return fail(FPM_E_ARG, "fpm_stitch: output too large");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t tile_bytes = (size_t)rows * cols * side * side * sizeof(float2);
+  const size_t out_bytes = (size_t)W * H * sizeof(float2);
+  fpm_status st = FPM_OK;
+  DevBuf scratch, tin, tout;
+  if (!hip_ok(scratch.alloc(stitch_scratch_bytes(rows, cols)), "hipMalloc(stitch scratch)", &st))
+    return st;
+  const float2* src = (const float2*)tiles;
+  float2* dst = (float2*)out;
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(tin.alloc(tile_bytes), "hipMalloc(stitch input)", &st) ||
+        !hip_ok(tout.alloc(out_bytes), "hipMalloc(stitch output)", &st) ||
+        !hip_ok(hipMemcpyAsync(tin.p, tiles, tile_bytes, hipMemcpyHostToDevice, s), "H2D tiles",
+                &st))
+      return st;
+    src = (const float2*)tin.p;
+    dst = (float2*)tout.p;
+  }
+  if (!hip_ok(launch_stitch(src, rows, cols, side, overlap, dst, scratch.p, s), "stitch kernels",
+              &st))
+    return st;
+  if (where == FPM_MEM_HOST &&
+      !hip_ok(hipMemcpyAsync(out, dst, out_bytes, hipMemcpyDeviceToHost, s), "D2H stitched", &st))
+    return st;
+  // the scratch (and staging) buffers are freed on return
+  if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
+  return FPM_OK;
+}
+
 fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, float* intensity,
                        fpm_mem where, void* hip_stream) {
   if (!plan || !object || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))

@@ -141,3 +141,11 @@ int mfma_box(int kx0, int nd);
 hipError_t launch_update_mfma(int n, int prec, const TileDev* tiles, const Item* items, int count,
                               int box_max, const uint16_t* E, const uint16_t* F, hipStream_t st);
 }  // namespace fpm
+
+namespace fpm {
+// Stitching (stitch.hip): scratch bytes for a rows x cols grid, and the
+// launches (strip sums, factor chains, composition) on `st`.
+size_t stitch_scratch_bytes(int rows, int cols);
+hipError_t launch_stitch(const float2* tiles, int rows, int cols, int side, int overlap,
+                         float2* out, void* scratch, hipStream_t st);
+}  // namespace fpm

@@ -218,3 +218,13 @@ def test_pipelined_levels_match_pixel_coverage(fpm, orc):
     t.schedule = fpm_synth.SCHED_LED_GROUPS
     i = fpm.Plan([t]).infos[0]
     assert i.levels == 3 * i.steps == 3 * i.ngroups
+
+
+def test_stitch_rejects_bad_arguments_without_gpu(fpm):
+    """Argument checks of fpm_stitch run before any device call."""
+    tiles = np.zeros(2 * 2 * 2 * 64 * 64, np.float32)
+    out = np.zeros(2 * 128 * 128, np.float32)
+    for args in [(2, 2, 64, 40), (0, 2, 64, 8), (2, 2, 64, -1), (2, 2, 1, 0)]:
+        with pytest.raises(fpm.FpmError) as e:
+            fpm.fpm_stitch(tiles, *args, out, fpm.FPM_MEM_HOST)
+        assert e.value.status == fpm.FPM_E_ARG
