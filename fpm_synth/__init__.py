@@ -225,3 +225,34 @@ def draw_object_and_defocus(td: TileDraw, z_range: Optional[float] = None) -> np
     if z_range is not None:
         td.desc.defocus_um = float(td.rng.uniform(-z_range, z_range))
     return td.obj
+
+
+def shared_object_tiles(tiles_per_side: int = 3, n: int = 64, overlap: int = 8,
+                        upsample: int = 4, iterations: int = 8,
+                        schedule: int = SCHED_LED_GROUPS, pupil_update: int = 0,
+                        workload: int = 1):
+    """Tiles cut from ONE object (the synthetic stand-in for the paper's
+    bee-wing field of Sec. 4.2): a (tiles_per_side)^2 grid of n-px tiles with
+    `overlap` LR pixels between neighbours (0: abutting tiles), each tile at
+    its own position under the LED array.  Returns (tile draws, the whole
+    high-resolution object, HR stride).  The object is drawn once from the
+    workload's first stream; tile t's draws use its own spawned stream."""
+    stride = n - overlap
+    span = stride * (tiles_per_side - 1) + n
+    ss = _root(workload).spawn(2)
+    rng0 = np.random.default_rng(ss[0])
+    whole = random_object(rng0, upsample * span)
+    seeds = ss[1].spawn(tiles_per_side * tiles_per_side)
+    out = []
+    pix = 1.625
+    for t in range(tiles_per_side * tiles_per_side):
+        ty, tx = divmod(t, tiles_per_side)
+        d = TileDesc(n=n, upsample=upsample, iterations=iterations, schedule=schedule,
+                     pupil_update=pupil_update)
+        d.tile_x_um = (stride * tx + n / 2 - span / 2) * pix
+        d.tile_y_um = (stride * ty + n / 2 - span / 2) * pix
+        td = TileDraw(desc=d, rng=np.random.default_rng(seeds[t]), peak_photons=1e4)
+        hs = upsample * stride
+        td.obj = whole[ty * hs:ty * hs + upsample * n, tx * hs:tx * hs + upsample * n].copy()
+        out.append(td)
+    return out, whole, upsample * stride
