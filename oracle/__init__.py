@@ -86,6 +86,8 @@ def lib():
         L.orc_reconstruct.argtypes = [gp, fp, C.c_int32, C.c_int32, C.c_int32,
                                       dp, dp, dp, dp, dp]
         L.orc_reconstruct.restype = C.c_int32
+        L.orc_reconstruct_online.argtypes = [gp, fp, C.c_int32, C.c_int32, ip, dp, dp, dp]
+        L.orc_reconstruct_online.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -212,6 +214,26 @@ def reconstruct(desc, I, iterations=None, pupil_update=None, schedule=None,
         None if Sin is None else _p(Sin, C.c_double),
         None if Pin is None else _p(Pin, C.c_double),
         _p(S, C.c_double), _p(P, C.c_double), _p(res, C.c_double))
+    return Result(S, P, res[:iters], int(st))
+
+
+def reconstruct_online(desc, I, arrival, iterations=None, pupil_update=None) -> Result:
+    """Sec. 3.4 Fig. 7a: the sequential reconstruction with the images
+    arriving in `arrival` (grid LED indices); see orc_reconstruct_online."""
+    g = geom(desc)
+    iters = desc.iterations if iterations is None else iterations
+    pu = desc.pupil_update if pupil_update is None else pupil_update
+    I = np.ascontiguousarray(I, dtype=np.float32)
+    arr = np.ascontiguousarray(arrival, dtype=np.int32)
+    if arr.size != desc.led_rows * desc.led_cols:
+        raise ValueError("arrival must list every LED once")
+    N = desc.n * desc.upsample
+    S = np.zeros((N, N), dtype=np.complex128)
+    P = np.zeros((desc.n, desc.n), dtype=np.complex128)
+    res = np.zeros(max(iters, 1), dtype=np.float64)
+    st = lib().orc_reconstruct_online(C.byref(g), _p(I, C.c_float), iters, pu,
+                                      _p(arr, C.c_int32), _p(S, C.c_double),
+                                      _p(P, C.c_double), _p(res, C.c_double))
     return Result(S, P, res[:iters], int(st))
 
 

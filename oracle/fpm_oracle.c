@@ -423,11 +423,16 @@ static void ap_step(orc_work *w, const int32_t *off, int j, const float *Ij,
     }
 }
 
-int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
-                        int32_t pupil_update, int32_t schedule, const double *S_in,
-                        const double *P_in, double *S_out, double *P_out, double *residual) {
+/* `first`: NULL for the offline sweep; else the order in which the L images
+ * arrive (online strategy, Sec. 3.4 Fig. 7a): the first arrival gives the
+ * initial guess and the first iteration updates in arrival order; later
+ * iterations follow the schedule's order over the complete stack. */
+static int32_t reconstruct(const orc_geom *g, const float *I, int32_t iterations,
+                           int32_t pupil_update, int32_t schedule, const int32_t *first,
+                           const double *S_in, const double *P_in, double *S_out,
+                           double *P_out, double *residual) {
   if (!g || !I || !S_out || !P_out || iterations < 0 || g->n <= 0 || g->n % 2 || g->up < 1 ||
-      schedule < 0 || schedule > 2)
+      schedule < 0 || schedule > 2 || (first && schedule != ORC_SEQUENTIAL))
     return -1;
   int n = g->n, N = g->n * g->up, L = g->led_rows * g->led_cols;
   size_t nn = (size_t)n * n, NN = (size_t)N * N;
@@ -466,7 +471,7 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
     memcpy(S, S_in, sizeof(double) * 2 * NN);
   } else {
     memset(S, 0, sizeof(double) * 2 * NN);
-    int j0 = order[0];
+    int j0 = first ? first[0] : order[0];
     for (size_t i = 0; i < nn; ++i) {
       double v = (double)I[(size_t)j0 * nn + i];
       w.phi[2 * i] = sqrt(v > 0.0 ? v : 0.0);
@@ -500,7 +505,8 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
       if (a > smax2) smax2 = a;
     }
     if (schedule == ORC_SEQUENTIAL || schedule == ORC_GROUP_ORDER) {
-      const int32_t *seq = (schedule == ORC_SEQUENTIAL) ? order : sweep;
+      const int32_t *seq = (schedule == ORC_SEQUENTIAL) ? (first && it == 0 ? first : order)
+                                                         : sweep;
       for (int k = 0; k < L; ++k) {
         int j = seq[k];
         memset(dP, 0, sizeof(double) * 2 * nn);
@@ -554,4 +560,29 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
   free(order);
   free(off);
   return 0;
+}
+
+int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
+                        int32_t pupil_update, int32_t schedule, const double *S_in,
+                        const double *P_in, double *S_out, double *P_out, double *residual) {
+  return reconstruct(g, I, iterations, pupil_update, schedule, NULL, S_in, P_in, S_out, P_out,
+                     residual);
+}
+
+int32_t orc_reconstruct_online(const orc_geom *g, const float *I, int32_t iterations,
+                               int32_t pupil_update, const int32_t *arrival, double *S_out,
+                               double *P_out, double *residual) {
+  if (!arrival) return -1;
+  const int L = g ? g->led_rows * g->led_cols : 0;
+  char *seen = (char *)calloc((size_t)(L > 0 ? L : 1), 1);
+  for (int k = 0; k < L; ++k) {
+    if (arrival[k] < 0 || arrival[k] >= L || seen[arrival[k]]) {
+      free(seen);
+      return -1;
+    }
+    seen[arrival[k]] = 1;
+  }
+  free(seen);
+  return reconstruct(g, I, iterations, pupil_update, ORC_SEQUENTIAL, arrival, NULL, NULL, S_out,
+                     P_out, residual);
 }

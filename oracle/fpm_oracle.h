@@ -87,6 +87,16 @@ int32_t orc_reconstruct(const orc_geom *g, const float *I, int32_t iterations,
                         const double *S_in, const double *P_in,
                         double *S_out, double *P_out, double *residual);
 
+/* Online reconstruction (Sec. 3.4, Fig. 7a), sequential schedule: the images
+ * arrive one LED at a time in `arrival` (a permutation of the L grid
+ * indices); the first arrival gives the initial guess, the first iteration
+ * updates in arrival order, later iterations in ascending-NA order.  Equal
+ * to orc_reconstruct(SEQUENTIAL) when `arrival` is that order.  Returns 0,
+ * -1 (bad arguments or `arrival` not a permutation), -2 (bad geometry). */
+int32_t orc_reconstruct_online(const orc_geom *g, const float *I, int32_t iterations,
+                               int32_t pupil_update, const int32_t *arrival,
+                               double *S_out, double *P_out, double *residual);
+
 #ifdef __cplusplus
 }
 #endif
