@@ -216,6 +216,68 @@ def single_tile_bench(fpm, reps: int = 5):
     return out
 
 
+def online_bench(fpm, tds, I, tiles_per_side: int, counts=(16, 256)):
+    """Online strategy (Sec. 3.4 Fig. 7a): the full-field tiles with the
+    sequential schedule, one LED's images of every tile pushed at a time (in
+    NA order, from device memory), each push running that LED's update on
+    all tiles; after the last push fpm_online_finish runs the remaining
+    iterations.  Per count of tiles (the centre block of the field): GPU time
+    per push (HIP events around each push, synchronised), the host time of a
+    push call, and the finish time."""
+    import dataclasses
+    import statistics
+    import torch
+
+    out = {}
+    n = tds[0].desc.n
+    L = tds[0].desc.led_rows * tds[0].desc.led_cols
+    Iv = I.view(len(tds), L, n * n)
+    for T in counts:
+        side = int(round(T ** 0.5))
+        if side * side != T or side > tiles_per_side:
+            continue
+        lo = (tiles_per_side - side) // 2
+        idx = [(lo + r) * tiles_per_side + lo + c for r in range(side) for c in range(side)]
+        descs = [dataclasses.replace(tds[t].desc, schedule=fpm.FPM_SCHED_SEQUENTIAL) for t in idx]
+        plan = fpm.Plan(descs)
+        order = plan.tables(0)[1]
+        imgs = Iv[idx].transpose(0, 1).contiguous()  # [L][tile][n*n]
+        obj, pup, res = fpm.device_buffers(plan)
+        fpm.fpm_online_begin(plan)  # setup and tuning outside the timing
+        for j in order:
+            fpm.fpm_online_push(plan, int(j), imgs[int(j)], fpm.FPM_MEM_DEVICE)
+        fpm.fpm_online_finish(plan, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        gpu_ms, host_ms = [], []
+        fpm.fpm_online_begin(plan)
+        for j in order:
+            torch.cuda.synchronize()
+            e0.record()
+            h0 = time.perf_counter()
+            fpm.fpm_online_push(plan, int(j), imgs[int(j)], fpm.FPM_MEM_DEVICE)
+            host_ms.append((time.perf_counter() - h0) * 1e3)
+            e1.record()
+            torch.cuda.synchronize()
+            gpu_ms.append(e0.elapsed_time(e1))
+        f0 = time.perf_counter()
+        fpm.fpm_online_finish(plan, fpm.FPM_MEM_DEVICE, obj, pup, res)
+        torch.cuda.synchronize()
+        fin_ms = (time.perf_counter() - f0) * 1e3
+        out[f"{T}_tiles"] = {
+            "tiles": T, "leds": L, "iterations": descs[0].iterations,
+            "push_gpu_ms_mean": round(statistics.mean(gpu_ms), 4),
+            "push_gpu_ms_median": round(statistics.median(gpu_ms), 4),
+            "push_gpu_ms_max": round(max(gpu_ms), 4),
+            "push_host_ms_median": round(statistics.median(host_ms), 4),
+            "first_iteration_gpu_ms": round(sum(gpu_ms), 3),
+            "finish_ms": round(fin_ms, 3),
+            "updates_per_push": T,
+        }
+        del plan, imgs, obj, pup, res
+    return out
+
+
 def uneven_objects(tds, device):
     """Seeded objects of every tile (host threads), packed on the device."""
     from concurrent.futures import ThreadPoolExecutor
@@ -546,6 +608,9 @@ def main():
     single = single_tile_bench(fpm)
     log("single tile: " + json.dumps(single))
 
+    online = online_bench(fpm, tds, I, args.tiles_per_side)
+    log("online: " + json.dumps(online))
+
     uneven = None
     if args.uneven_tiles > 0:
         uneven = uneven_bench(fpm, args.uneven_tiles, steps=1, warmup=1)
@@ -585,6 +650,7 @@ def main():
         "rel_l2_vs_oracle": {"tiles": sample, **errs} if sample else None,
         "stitch": stitch,
         "single_tile": single,
+        "online": online,
         "uneven_batch": uneven,
         "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},

@@ -47,7 +47,8 @@ typedef enum {
   FPM_E_DEVICE = -4,      /* a HIP call failed                                */
   FPM_E_DIVERGED = -5,    /* a residual became non-finite                     */
   FPM_E_CANCELLED = -6,   /* the request was cancelled                        */
-  FPM_E_UNSUPPORTED = -7  /* tile size or precision this build does not run   */
+  FPM_E_UNSUPPORTED = -7, /* tile size or precision this build does not run   */
+  FPM_E_STATE = -8        /* call out of order (online session open/closed)   */
 } fpm_status;
 
 /* Arithmetic of the two n x n transforms of every update.  The MFMA forms
@@ -193,6 +194,41 @@ fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
 fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem where,
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
+
+/* Online reconstruction (Sec. 3.4, Fig. 7a): the images of one LED arrive
+ * at a time, and each arrival runs that LED's update on every tile at once,
+ * so the first iteration proceeds while the next LED pattern is set up.
+ * Every tile of the plan must use FPM_SCHED_SEQUENTIAL and the same L
+ * (FPM_E_ARG otherwise).
+ *   fpm_online_begin: opens a session on `plan` (device state, tuning and
+ *     the first-iteration work lists are set up here, not in the pushes).
+ *     While it is open, fpm_reconstruct and fpm_profile_reconstruct on the
+ *     plan return FPM_E_STATE; begin again restarts the session.
+ *   fpm_online_push: `intensity` float [tile][n][n], the tiles' images for
+ *     LED `led` (grid index), in plan tile order (each tile its own n).
+ *     Each LED once, any order (FPM_E_ARG for a repeat or out of range).  The
+ *     first pushed image is the initial guess (its LED plays j0 of
+ *     fpm_reconstruct); each push then runs the update of Fig. 2 for `led`
+ *     on every tile, in arrival order.  After the L-th push the first
+ *     iteration's residual and normalisation follow.  FPM_MEM_HOST: the
+ *     image is validated and copied into pinned staging, the call returns
+ *     without waiting for the GPU (it waits only for the previous push's
+ *     copy to leave the staging); FPM_MEM_DEVICE: the buffer must stay valid
+ *     until the stream has run the push.  Enqueued on `hip_stream`.
+ *   fpm_online_finish: once all L LEDs are pushed (FPM_E_STATE before),
+ *     runs iterations 2.. in the plan's sweep order over the whole stack and
+ *     writes the outputs as fpm_reconstruct does (same layouts and `where`
+ *     rules); closes the session and synchronises the stream.
+ *   fpm_online_abort: closes an open session without outputs (synchronises
+ *     the device); a no-op when none is open.
+ * With pushes in the plan's sweep order the result is bitwise that of
+ * fpm_reconstruct.  All calls of one session go to one stream. */
+fpm_status fpm_online_begin(fpm_plan_t *plan, void *hip_stream);
+fpm_status fpm_online_push(fpm_plan_t *plan, int32_t led, const float *intensity,
+                           fpm_mem where, void *hip_stream);
+fpm_status fpm_online_finish(fpm_plan_t *plan, fpm_mem where, void *object_out,
+                             void *pupil_out, double *residual_out, void *hip_stream);
+fpm_status fpm_online_abort(fpm_plan_t *plan);
 
 /* Stitch reconstructed tiles into one field of view (Sec. 3.1, Eq. (1)).
  *   tiles  complex64 [rows][cols][side][side]: the tile objects on their grid,

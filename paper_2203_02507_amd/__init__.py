@@ -25,20 +25,21 @@ LIB_PATH = os.path.join(_HERE, "libfpm.so")
 
 FPM_OK, FPM_PENDING = 0, 1
 FPM_E_ARG, FPM_E_GEOMETRY, FPM_E_NOMEM, FPM_E_DEVICE = -1, -2, -3, -4
-FPM_E_DIVERGED, FPM_E_CANCELLED, FPM_E_UNSUPPORTED = -5, -6, -7
+FPM_E_DIVERGED, FPM_E_CANCELLED, FPM_E_UNSUPPORTED, FPM_E_STATE = -5, -6, -7, -8
 FPM_MEM_HOST, FPM_MEM_DEVICE = 0, 1
 FPM_SCHED_SEQUENTIAL, FPM_SCHED_LED_GROUPS, FPM_SCHED_GROUP_ORDER, FPM_SCHED_PIPELINED = 0, 1, 2, 3
 FPM_PREC_FP32_FFT, FPM_PREC_MFMA_BF16X3, FPM_PREC_MFMA_FP16 = 0, 1, 2
 
 STATUS_NAMES = {0: "FPM_OK", 1: "FPM_PENDING", -1: "FPM_E_ARG", -2: "FPM_E_GEOMETRY",
                 -3: "FPM_E_NOMEM", -4: "FPM_E_DEVICE", -5: "FPM_E_DIVERGED",
-                -6: "FPM_E_CANCELLED", -7: "FPM_E_UNSUPPORTED"}
+                -6: "FPM_E_CANCELLED", -7: "FPM_E_UNSUPPORTED", -8: "FPM_E_STATE"}
 
 # every entry point declared in include/fpm.h
 EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_tables",
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
-           "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch")
+           "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch",
+           "fpm_online_begin", "fpm_online_push", "fpm_online_finish", "fpm_online_abort")
 
 
 class FpmError(RuntimeError):
@@ -121,6 +122,14 @@ def _load():
     L.fpm_profile_reconstruct.restype = C.c_int
     L.fpm_stitch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int, vp]
     L.fpm_stitch.restype = C.c_int
+    L.fpm_online_begin.argtypes = [vp, vp]
+    L.fpm_online_begin.restype = C.c_int
+    L.fpm_online_push.argtypes = [vp, C.c_int32, vp, C.c_int, vp]
+    L.fpm_online_push.restype = C.c_int
+    L.fpm_online_finish.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+    L.fpm_online_finish.restype = C.c_int
+    L.fpm_online_abort.argtypes = [vp]
+    L.fpm_online_abort.restype = C.c_int
     L.fpm_last_error.argtypes = []
     L.fpm_last_error.restype = C.c_char_p
     L.fpm_version.argtypes = []
@@ -267,6 +276,29 @@ def fpm_reconstruct(plan: Plan, intensity, where: int, object_out=None, pupil_ou
     return check(lib.fpm_reconstruct(plan.handle, _ptr(intensity, where), where,
                                      _ptr(object_out, where), _ptr(pupil_out, where),
                                      _ptr(residual_out, where), _stream(stream)))
+
+
+def fpm_online_begin(plan: Plan, stream=None) -> int:
+    """Sec. 3.4 Fig. 7a: open an online session on `plan`."""
+    return check(lib.fpm_online_begin(plan.handle, _stream(stream)))
+
+
+def fpm_online_push(plan: Plan, led: int, intensity, where: int, stream=None) -> int:
+    """The tiles' images of LED `led`, float [tile][n][n]; runs that LED's
+    update on every tile."""
+    return check(lib.fpm_online_push(plan.handle, led, _ptr(intensity, where), where,
+                                     _stream(stream)))
+
+
+def fpm_online_finish(plan: Plan, where: int, object_out=None, pupil_out=None,
+                      residual_out=None, stream=None) -> int:
+    return check(lib.fpm_online_finish(plan.handle, where, _ptr(object_out, where),
+                                       _ptr(pupil_out, where), _ptr(residual_out, where),
+                                       _stream(stream)))
+
+
+def fpm_online_abort(plan: Plan) -> int:
+    return check(lib.fpm_online_abort(plan.handle))
 
 
 def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:

@@ -48,6 +48,68 @@ fpm_status ensure_setup(fpm_plan_t* p) {
   return p->exec.setup(p->tiles);
 }
 
+// Object (finalised), pupil and residual history of every tile into the
+// caller's buffers; host mode synchronises and checks the residuals.
+fpm_status collect_outputs(fpm_plan_t* plan, fpm_mem where, void* object_out, void* pupil_out,
+                           double* residual_out, hipStream_t s) {
+  Executor& ex = plan->exec;
+  fpm_status st = FPM_OK;
+  const hipMemcpyKind d2o = where == FPM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (object_out) {
+    if (!hip_ok(ex.enqueue_finalize(s), "finalise", &st) ||
+        !hip_ok(hipMemcpyAsync(object_out, ex.obj_stage.p, sizeof(float2) * ex.total_obj, d2o, s),
+                "copy object", &st))
+      return st;
+  }
+  if (pupil_out) {
+    if (where == FPM_MEM_DEVICE) {
+      if (!hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, pupil_out,
+                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
+                  "gather pupil", &st))
+        return st;
+    } else {
+      if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
+          !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.pupil_stage.p,
+                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
+                  "gather pupil", &st) ||
+          !hip_ok(hipMemcpyAsync(pupil_out, ex.pupil_stage.p, sizeof(float2) * ex.total_pupil,
+                                 d2o, s),
+                  "copy pupil", &st))
+        return st;
+    }
+  }
+  std::vector<double> res_host;
+  const bool want_res_host = where == FPM_MEM_HOST;
+  if (residual_out || want_res_host) {
+    if (!hip_ok(ex.res_stage.alloc(sizeof(double) * std::max<int64_t>(1, ex.total_res)),
+                "hipMalloc", &st) ||
+        !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.res_stage.p,
+                              (const int64_t*)ex.r_off_d.p, 3, ex.n_max, s),
+                "gather residual", &st))
+      return st;
+    if (residual_out && where == FPM_MEM_DEVICE &&
+        !hip_ok(hipMemcpyAsync(residual_out, ex.res_stage.p, sizeof(double) * ex.total_res,
+                               hipMemcpyDeviceToDevice, s),
+                "copy residual", &st))
+      return st;
+    if (want_res_host) {
+      res_host.resize(std::max<int64_t>(1, ex.total_res));
+      if (!hip_ok(hipMemcpyAsync(res_host.data(), ex.res_stage.p, sizeof(double) * ex.total_res,
+                                 hipMemcpyDeviceToHost, s),
+                  "copy residual", &st))
+        return st;
+    }
+  }
+  if (where == FPM_MEM_HOST) {
+    if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
+    for (int64_t i = 0; i < ex.total_res; ++i)
+      if (!std::isfinite(res_host[i]))
+        return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
+    if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
+  }
+  return FPM_OK;
+}
+
 }  // namespace
 }  // namespace fpm
 
@@ -226,6 +288,8 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   if (!plan || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_reconstruct: NULL argument or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
+  if (plan->exec.online_count >= 0)
+    return fail(FPM_E_STATE, "fpm_reconstruct: an online session holds the plan");
   DeviceGuard g(plan);
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_reconstruct: cannot select the plan's device");
   fpm_status st = ensure_setup(plan);
@@ -252,59 +316,159 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
               "set intensity", &st))
     return st;
   if (!hip_ok(ex.run(s, use_graphs()), "reconstruction sweep", &st)) return st;
-  const hipMemcpyKind d2o = where == FPM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  if (object_out) {
-    if (!hip_ok(ex.enqueue_finalize(s), "finalise", &st) ||
-        !hip_ok(hipMemcpyAsync(object_out, ex.obj_stage.p, sizeof(float2) * ex.total_obj, d2o, s),
-                "copy object", &st))
-      return st;
+  return collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
+}
+
+fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) {
+  if (!plan) return fail(FPM_E_ARG, "fpm_online_begin: NULL plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  const int L = plan->tiles[0].L;
+  for (size_t t = 0; t < plan->tiles.size(); ++t) {
+    const TilePlan& tp = plan->tiles[t];
+    if (tp.d.schedule != FPM_SCHED_SEQUENTIAL)
+      return fail(FPM_E_ARG, "fpm_online_begin: tile " + std::to_string(t) +
+                                 " is not FPM_SCHED_SEQUENTIAL (one image, one update)");
+    if (tp.L != L)
+      return fail(FPM_E_ARG, "fpm_online_begin: tiles differ in LED count (" +
+                                 std::to_string(tp.L) + " vs " + std::to_string(L) + ")");
   }
-  if (pupil_out) {
-    if (where == FPM_MEM_DEVICE) {
-      if (!hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, pupil_out,
-                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
-                  "gather pupil", &st))
-        return st;
-    } else {
-      if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
-          !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.pupil_stage.p,
-                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
-                  "gather pupil", &st) ||
-          !hip_ok(hipMemcpyAsync(pupil_out, ex.pupil_stage.p, sizeof(float2) * ex.total_pupil,
-                                 d2o, s),
-                  "copy pupil", &st))
-        return st;
-    }
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_begin: cannot select the plan's device");
+  fpm_status st = ensure_setup(plan);
+  if (st != FPM_OK) return st;
+  Executor& ex = plan->exec;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!ex.tuned) {
+    // variant timing scribbles on state that the first push initialises
+    if (!hip_ok(ex.tune(s), "update-kernel tuning", &st)) return st;
+    ex.tuned = true;
   }
-  std::vector<double> res_host;
-  const bool want_res_host = where == FPM_MEM_HOST;
-  if (residual_out || want_res_host) {
-    if (!hip_ok(ex.res_stage.alloc(sizeof(double) * std::max<int64_t>(1, ex.total_res)),
-                "hipMalloc", &st) ||
-        !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.res_stage.p,
-                              (const int64_t*)ex.r_off_d.p, 3, ex.n_max, s),
-                "gather residual", &st))
-      return st;
-    if (residual_out && where == FPM_MEM_DEVICE &&
-        !hip_ok(hipMemcpyAsync(residual_out, ex.res_stage.p, sizeof(double) * ex.total_res,
-                               hipMemcpyDeviceToDevice, s),
-                "copy residual", &st))
-      return st;
-    if (want_res_host) {
-      res_host.resize(std::max<int64_t>(1, ex.total_res));
-      if (!hip_ok(hipMemcpyAsync(res_host.data(), ex.res_stage.p, sizeof(double) * ex.total_res,
-                                 hipMemcpyDeviceToHost, s),
-                  "copy residual", &st))
-        return st;
-    }
-  }
+  if (ex.online_launch.empty() && (st = ex.online_setup(plan->tiles)) != FPM_OK) return st;
+  if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, (const float*)ex.online_I.p,
+                                   (const int64_t*)ex.i_off_d.p, s),
+              "bind online stack", &st))
+    return st;
+  ex.online_pushed.assign(L, 0);
+  ex.online_count = 0;
+  return FPM_OK;
+}
+
+fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity, fpm_mem where,
+                           void* hip_stream) {
+  if (!plan || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_online_push: NULL argument or bad memory kind");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Executor& ex = plan->exec;
+  if (ex.online_count < 0) return fail(FPM_E_STATE, "fpm_online_push: no online session");
+  const int L = (int)ex.online_pushed.size();
+  if (led < 0 || led >= L)
+    return fail(FPM_E_ARG, "fpm_online_push: LED " + std::to_string(led) + " out of range");
+  if (ex.online_pushed[led])
+    return fail(FPM_E_ARG, "fpm_online_push: LED " + std::to_string(led) + " already pushed");
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_push: cannot select the plan's device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  fpm_status st = FPM_OK;
+  const size_t bytes = sizeof(float) * ex.online_push_floats;
+  const float* src = intensity;
   if (where == FPM_MEM_HOST) {
-    if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
-    for (int64_t i = 0; i < ex.total_res; ++i)
-      if (!std::isfinite(res_host[i]))
-        return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
-    if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
+    for (int64_t i = 0; i < ex.online_push_floats; ++i) {
+      const float v = intensity[i];
+      if (!(v >= 0.0f) || !std::isfinite(v))
+        return fail(FPM_E_ARG, "fpm_online_push: intensity " + std::to_string(i) +
+                                   " is negative or not finite");
+    }
+    // the pinned staging buffer is free once the previous push's copy has run
+    if (ex.online_ev_armed &&
+        !hip_ok(hipEventSynchronize(ex.online_ev), "hipEventSynchronize", &st))
+      return st;
+    std::memcpy(ex.online_pin, intensity, bytes);
+    if (!hip_ok(hipMemcpyAsync(ex.online_stage.p, ex.online_pin, bytes, hipMemcpyHostToDevice, s),
+                "H2D image", &st) ||
+        !hip_ok(hipEventRecord(ex.online_ev, s), "hipEventRecord", &st))
+      return st;
+    ex.online_ev_armed = true;
+    src = (const float*)ex.online_stage.p;
   }
+  TileDev* tab = (TileDev*)ex.table.p;
+  if (!hip_ok(launch_online_scatter(tab, ex.ntiles, src, (const int64_t*)ex.online_src_off_d.p,
+                                    (float*)ex.online_I.p, (const int64_t*)ex.i_off_d.p, led, s),
+              "scatter image", &st))
+    return st;
+  if (ex.online_count == 0) {
+    // the first image is the initial guess (Sec. 2.1 step 1): its LED plays j0
+    if (!hip_ok(launch_set_j0(tab, ex.ntiles, led, s), "set first LED", &st) ||
+        !hip_ok(ex.enqueue_range(0, 1, s), "initial state", &st))
+      return st;
+  }
+  for (int c = 0; c < ex.online_classes; ++c) {
+    const Launch& l = ex.online_launch[(size_t)led * ex.online_classes + c];
+    if (l.count > 0 &&
+        !hip_ok(launch_update_class(l, tab, (const Item*)ex.online_items_d.p + l.off, s),
+                "update", &st))
+      return st;
+  }
+  ex.online_pushed[led] = 1;
+  if (++ex.online_count == L) {
+    // iteration 0 is complete: its residual, and the spectrum maximum the
+    // next iteration's pupil steps divide by
+    const size_t end0 = ex.iter_first_launch.size() > 1 ? (size_t)ex.iter_first_launch[1]
+                                                        : ex.launches.size();
+    for (size_t li = (size_t)ex.iter_first_launch[0]; li < end0; ++li) {
+      const Launch::Kind k = ex.launches[li].kind;
+      if ((k == Launch::ITER_END || k == Launch::SMAX) &&
+          !hip_ok(ex.enqueue_range(li, li + 1, s), "iteration end", &st))
+        return st;
+    }
+  }
+  return FPM_OK;
+}
+
+fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, void* pupil_out,
+                             double* residual_out, void* hip_stream) {
+  if (!plan || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
+    return fail(FPM_E_ARG, "fpm_online_finish: NULL plan or bad memory kind");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Executor& ex = plan->exec;
+  if (ex.online_count < 0) return fail(FPM_E_STATE, "fpm_online_finish: no online session");
+  if (ex.online_count < (int)ex.online_pushed.size())
+    return fail(FPM_E_STATE, "fpm_online_finish: " + std::to_string(ex.online_count) + " of " +
+                                 std::to_string(ex.online_pushed.size()) + " LEDs pushed");
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_finish: cannot select the plan's device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  fpm_status st = FPM_OK;
+  // iterations 1.. over the whole stack, in the plan's order
+  if (ex.iter_first_launch.size() > 1 &&
+      !hip_ok(ex.enqueue_range((size_t)ex.iter_first_launch[1], ex.launches.size(), s),
+              "remaining iterations", &st))
+    return st;
+  ex.online_count = -1;
+  st = collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
+  // the plan's own first LED again for later fpm_reconstruct calls
+  fpm_status st2 = FPM_OK;
+  if (!hip_ok(hipMemcpyAsync(ex.table.p, ex.host_tiles.data(),
+                             sizeof(TileDev) * ex.host_tiles.size(), hipMemcpyHostToDevice, s),
+              "restore tile table", &st2) ||
+      !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st2))
+    return st != FPM_OK ? st : st2;
+  return st;
+}
+
+fpm_status fpm_online_abort(fpm_plan_t* plan) {
+  if (!plan) return fail(FPM_E_ARG, "fpm_online_abort: NULL plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Executor& ex = plan->exec;
+  if (ex.online_count < 0) return FPM_OK;
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_abort: cannot select the plan's device");
+  fpm_status st = FPM_OK;
+  ex.online_count = -1;
+  if (!hip_ok(hipDeviceSynchronize(), "hipDeviceSynchronize", &st) ||
+      !hip_ok(hipMemcpy(ex.table.p, ex.host_tiles.data(), sizeof(TileDev) * ex.host_tiles.size(),
+                        hipMemcpyHostToDevice),
+              "restore tile table", &st))
+    return st;
   return FPM_OK;
 }
 
@@ -312,6 +476,8 @@ fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
                                    fpm_kernel_time* out, void* hip_stream) {
   if (!plan || !intensity || !out) return fail(FPM_E_ARG, "fpm_profile_reconstruct: NULL argument");
   std::lock_guard<std::mutex> lk(plan->mu);
+  if (plan->exec.online_count >= 0)
+    return fail(FPM_E_STATE, "fpm_profile_reconstruct: an online session holds the plan");
   DeviceGuard g(plan);
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_profile_reconstruct: cannot select the plan's device");
   fpm_status st = ensure_setup(plan);

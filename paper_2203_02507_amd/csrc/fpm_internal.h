@@ -124,6 +124,12 @@ hipError_t launch_object_to_spectrum(const TileDev* tiles, int count, const floa
 // table[t].I = base + i_off[t]   (kernel argument, so no host buffer outlives the call)
 hipError_t launch_set_intensity(TileDev* table, int count, const float* base,
                                 const int64_t* i_off, hipStream_t st);
+// stack[i_off[t] + led n_t^2 ...] <- src[src_off[t] ...], n_t^2 floats per tile
+hipError_t launch_online_scatter(const TileDev* table, int count, const float* src,
+                                 const int64_t* src_off, float* stack, const int64_t* i_off,
+                                 int led, hipStream_t st);
+// table[t].j0 = j0 for every tile (the first LED of an online session)
+hipError_t launch_set_j0(TileDev* table, int count, int j0, hipStream_t st);
 // dst[off[t] + i] = tile t's pupil (which = 1), initial pupil (which = 2) or
 // residual history (which = 3, doubles)
 hipError_t launch_gather(const TileDev* tiles, int count, void* dst, const int64_t* off,

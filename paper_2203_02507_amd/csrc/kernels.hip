@@ -1152,6 +1152,26 @@ __global__ __launch_bounds__(256) void obj_mod_kernel(const TileDev* __restrict_
   }
 }
 
+// one LED's images of every tile into the stacks: block t copies tile t's
+// n^2 floats from src + src_off[t] to stack + i_off[t] + led n^2
+__global__ __launch_bounds__(256) void online_scatter_kernel(const TileDev* __restrict__ table,
+                                                             const float* __restrict__ src,
+                                                             const int64_t* __restrict__ src_off,
+                                                             float* __restrict__ stack,
+                                                             const int64_t* __restrict__ i_off,
+                                                             int led) {
+  const int t = blockIdx.x;
+  const int nn = table[t].n * table[t].n;
+  const float* s = src + src_off[t];
+  float* d = stack + i_off[t] + (size_t)led * nn;
+  for (int i = threadIdx.x; i < nn; i += 256) d[i] = s[i];
+}
+
+__global__ void set_j0_kernel(TileDev* __restrict__ table, int count, int j0) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) table[t].j0 = j0;
+}
+
 __global__ void set_intensity_kernel(TileDev* __restrict__ table, int count,
                                      const float* __restrict__ base,
                                      const int64_t* __restrict__ i_off) {
@@ -1341,6 +1361,21 @@ hipError_t launch_object_to_spectrum(const TileDev* tiles, int count, const floa
   if (count <= 0) return hipSuccess;
   const int chunks = (int)(((size_t)N_max * N_max + 256 * 16 - 1) / (256 * 16));
   hipLaunchKernelGGL(obj_mod_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, src_base, src_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_online_scatter(const TileDev* table, int count, const float* src,
+                                 const int64_t* src_off, float* stack, const int64_t* i_off,
+                                 int led, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(online_scatter_kernel, dim3(count), dim3(256), 0, st, table, src, src_off,
+                     stack, i_off, led);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_j0(TileDev* table, int count, int j0, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_j0_kernel, dim3((count + 255) / 256), dim3(256), 0, st, table, count, j0);
   return hipGetLastError();
 }
 

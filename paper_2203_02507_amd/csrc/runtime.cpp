@@ -90,6 +90,8 @@ hipError_t DevBuf::alloc(size_t n) {
 Executor::~Executor() {
   if (graph_exec) hipGraphExecDestroy(graph_exec);
   if (cap_stream) hipStreamDestroy(cap_stream);
+  if (online_ev) hipEventDestroy(online_ev);
+  if (online_pin) hipHostFree(online_pin);
 }
 
 namespace {
@@ -220,11 +222,13 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   }
   std::vector<int> prev_active;
   int reuse_from = -1;  // first launch index of the previous iteration body
+  iter_first_launch.clear();
   for (int k = 0; k < max_iter; ++k) {
     std::vector<int> active;
     for (int t = 0; t < T; ++t)
       if (tiles[t].d.iterations > k && !piped(tiles[t])) active.push_back(t);
     const int body_start = (int)launches.size();
+    iter_first_launch.push_back(body_start);
     if (k > 0 && active == prev_active && reuse_from >= 0) {
       // identical work lists: replay the previous iteration's launches
       const int body_len = body_start - reuse_from;
@@ -591,14 +595,17 @@ hipError_t Executor::profile(hipStream_t s, fpm_kernel_time* out) {
   return e;
 }
 
-hipError_t Executor::enqueue_sweep(hipStream_t s) {
+hipError_t Executor::enqueue_sweep(hipStream_t s) { return enqueue_range(0, launches.size(), s); }
+
+hipError_t Executor::enqueue_range(size_t begin, size_t end, hipStream_t s) {
   const TileDev* tab = (const TileDev*)table.p;
   const Item* it = (const Item*)items_d.p;
   const StepTile* stp = (const StepTile*)steps_d.p;
   const int* ids = (const int*)ids_d.p;
   const LineJob* jobs = (const LineJob*)jobs_d.p;
   hipError_t e = hipSuccess;
-  for (const Launch& l : launches) {
+  for (size_t li = begin; li < end && li < launches.size(); ++li) {
+    const Launch& l = launches[li];
     switch (l.kind) {
       case Launch::INIT: {
         e = launch_init_state(tab, ids + l.off, l.count, 0, (int)std::sqrt((double)NN_max), s);
@@ -707,6 +714,80 @@ hipError_t Executor::run(hipStream_t s, bool use_graph) {
 
 namespace fpm {
 
+fpm_status Executor::online_setup(const std::vector<TilePlan>& tiles) {
+  fpm_status st = FPM_OK;
+  const int T = (int)tiles.size();
+  const int L = tiles[0].L;
+  // update classes in a fixed order, as in the sweep
+  std::map<std::pair<int, int>, std::pair<int, int>> ucls;
+  for (const TilePlan& tp : tiles) {
+    auto& u = ucls[{tp.n, tp.d.precision}];
+    u.first = std::max(u.first, tp.nd);
+    u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
+  }
+  online_classes = (int)ucls.size();
+  std::vector<Item> items;
+  online_launch.clear();
+  for (int j = 0; j < L; ++j)
+    for (auto& kv : ucls) {
+      Launch l{};
+      l.kind = Launch::UPDATE;
+      l.n = kv.first.first;
+      l.prec = kv.first.second;
+      l.nd_max = kv.second.first;
+      l.box_max = kv.second.second;
+      if (l.n == 256) l.big_scratch = (float2*)big_scratch.p;
+      if (l.prec != FPM_PREC_FP32_FFT &&
+          !hip_ok(dft_tables(l.n, l.prec, &l.tabE, &l.tabF), "DFT tables", &st))
+        return st;
+      l.off = (int)items.size();
+      for (int t = 0; t < T; ++t) {
+        const TilePlan& tp = tiles[t];
+        if (tp.n != l.n || tp.d.precision != l.prec) continue;
+        Item it{};
+        it.tile = t;
+        it.led = j;
+        it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+        it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+        it.slot = 0;
+        it.gsize = 1;
+        it.iter = 0;
+        items.push_back(it);
+      }
+      l.count = (int)items.size() - l.off;
+      online_launch.push_back(l);
+    }
+  if (!hip_ok(online_items_d.alloc(sizeof(Item) * std::max<size_t>(1, items.size())),
+              "hipMalloc(online items)", &st) ||
+      !hip_ok(hipMemcpy(online_items_d.p, items.data(), sizeof(Item) * items.size(),
+                        hipMemcpyHostToDevice),
+              "hipMemcpy(online items)", &st))
+    return st;
+  // where each tile's image sits in one push: tiles in order, n^2 floats each
+  std::vector<int64_t> src_off(T);
+  online_push_floats = 0;
+  for (int t = 0; t < T; ++t) {
+    src_off[t] = online_push_floats;
+    online_push_floats += (int64_t)tiles[t].n * tiles[t].n;
+  }
+  if (!hip_ok(online_src_off_d.alloc(sizeof(int64_t) * T), "hipMalloc(online offsets)", &st) ||
+      !hip_ok(hipMemcpy(online_src_off_d.p, src_off.data(), sizeof(int64_t) * T,
+                        hipMemcpyHostToDevice),
+              "hipMemcpy(online offsets)", &st) ||
+      !hip_ok(online_I.alloc(sizeof(float) * total_I), "hipMalloc(online stack)", &st) ||
+      !hip_ok(online_stage.alloc(sizeof(float) * online_push_floats), "hipMalloc(online stage)",
+              &st))
+    return st;
+  if (!online_pin &&
+      !hip_ok(hipHostMalloc(&online_pin, sizeof(float) * online_push_floats, hipHostMallocDefault),
+              "hipHostMalloc(online stage)", &st))
+    return st;
+  if (!online_ev && !hip_ok(hipEventCreateWithFlags(&online_ev, hipEventDisableTiming),
+                            "hipEventCreate", &st))
+    return st;
+  return FPM_OK;
+}
+
 hipError_t Executor::enqueue_finalize(hipStream_t s) {
   const TileDev* tab = (const TileDev*)table.p;
   const LineJob* jobs = (const LineJob*)jobs_d.p;
@@ -740,7 +821,8 @@ hipError_t Executor::enqueue_forward(const float2* obj_src, float* out, hipStrea
 size_t Executor::device_bytes() const {
   const DevBuf* all[] = {&state, &table, &items_d, &ranges_d, &steps_d, &ids_d, &jobs_d, &i_off_d, &o_off_d,
                          &p_off_d, &r_off_d, &obj_stage, &fwd_P, &fwd_table, &fwd_items,
-                         &I_stage, &res_stage, &pupil_stage, &big_scratch};
+                         &I_stage, &res_stage, &pupil_stage, &big_scratch, &online_I,
+                         &online_items_d, &online_src_off_d, &online_stage};
   size_t b = 0;
   for (const DevBuf* d : all) b += d->bytes;
   return b;

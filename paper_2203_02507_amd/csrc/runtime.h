@@ -81,13 +81,31 @@ struct Executor {
     int n, nd_max, off, count;
   };
   std::vector<FwdLaunch> fwd_launches;
-  const float* I_bound = nullptr;  // intensity base the table currently points at
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+
+  // first launch of each iteration of the iteration-aligned sweep
+  std::vector<int> iter_first_launch;
+  // online reconstruction (one LED's images at a time): the stack the pushes
+  // fill, per-(LED, class) update launches of iteration 0 over every tile
+  DevBuf online_I, online_items_d, online_src_off_d, online_stage;
+  std::vector<Launch> online_launch;  // [led][class]
+  int online_classes = 0;
+  int64_t online_push_floats = 0;     // floats of one push: sum over tiles of n^2
+  std::vector<char> online_pushed;
+  int online_count = -1;  // -1: no online session
+  // host pushes: pinned staging, reused once the previous copy has left it
+  void* online_pin = nullptr;
+  hipEvent_t online_ev = nullptr;
+  bool online_ev_armed = false;
 
   ~Executor();
   fpm_status setup(const std::vector<TilePlan>& tiles);
   hipError_t enqueue_sweep(hipStream_t s);
+  // launches [begin, end) of the sweep, eagerly
+  hipError_t enqueue_range(size_t begin, size_t end, hipStream_t s);
+  // online session: per-(LED, class) launches over all tiles (iteration 0)
+  fpm_status online_setup(const std::vector<TilePlan>& tiles);
   hipError_t run(hipStream_t s, bool use_graph);
   // time every update-kernel variant on this plan's largest launch of each
   // tile size (before the state is initialised) and keep the fastest

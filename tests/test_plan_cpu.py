@@ -228,3 +228,28 @@ def test_stitch_rejects_bad_arguments_without_gpu(fpm):
         with pytest.raises(fpm.FpmError) as e:
             fpm.fpm_stitch(tiles, *args, out, fpm.FPM_MEM_HOST)
         assert e.value.status == fpm.FPM_E_ARG
+
+
+def test_online_session_state_checks_without_gpu(fpm):
+    """The online calls check the session state and the schedule on the host
+    before any device call: push / finish without a session -> FPM_E_STATE,
+    a non-sequential tile or unequal LED counts -> FPM_E_ARG, abort of no
+    session -> OK."""
+    d = fpm_synth.single_tile_64(iterations=1)[0].desc
+    plan = fpm.Plan([d])
+    img = np.ones((64, 64), np.float32)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_online_push(plan, 0, img, fpm.FPM_MEM_HOST)
+    assert e.value.status == fpm.FPM_E_STATE
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_online_finish(plan, fpm.FPM_MEM_HOST)
+    assert e.value.status == fpm.FPM_E_STATE
+    assert fpm.fpm_online_abort(plan) == fpm.FPM_OK
+    g = fpm_synth.single_tile_64(iterations=1, schedule=fpm_synth.SCHED_LED_GROUPS)[0].desc
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_online_begin(fpm.Plan([d, g]))
+    assert e.value.status == fpm.FPM_E_ARG
+    small = fpm_synth.TileDesc(n=64, upsample=4, led_rows=5, led_cols=5, iterations=1)
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_online_begin(fpm.Plan([d, small]))
+    assert e.value.status == fpm.FPM_E_ARG
