@@ -466,6 +466,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-online", action="store_true")
     ap.add_argument("--precisions", default="1,2",
                     help="MFMA precision variants timed beside the FP32 path (comma list, "
                          "empty for none)")
@@ -608,8 +609,10 @@ def main():
     single = single_tile_bench(fpm)
     log("single tile: " + json.dumps(single))
 
-    online = online_bench(fpm, tds, I, args.tiles_per_side)
-    log("online: " + json.dumps(online))
+    online = None
+    if not args.no_online:
+        online = online_bench(fpm, tds, I, args.tiles_per_side)
+        log("online: " + json.dumps(online))
 
     uneven = None
     if args.uneven_tiles > 0:

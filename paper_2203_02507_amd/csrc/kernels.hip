@@ -84,11 +84,14 @@ __device__ constexpr TwTab<M> kTw{};
 // ------------------------------------------------------- complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// This file is compiled without floating-point contraction: every fused
+// multiply-add is written out, so that two kernels running the same steps on
+// a line (whatever their layout) round identically.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // products with the fused multiply-add placed explicitly (no contraction
@@ -99,7 +102,7 @@ __device__ __forceinline__ float2 cmul_fma(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmulc_fma(float2 a, float2 b) {  // a * conj(b)
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
-__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
 // multiply by W_len^k (INV: exp(+2 pi i k/len), else exp(-2 pi i k/len));
 // k and len are compile-time after unrolling.
@@ -110,7 +113,7 @@ __device__ __forceinline__ float2 tw_mul(float2 v, int k, int len) {
   const int idx = k * (R / len);
   const float c = kTw<R>.c[idx];
   const float s = INV ? kTw<R>.s[idx] : -kTw<R>.s[idx];
-  return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  return make_float2(fmaf(v.x, c, -(v.y * s)), fmaf(v.x, s, v.y * c));
 }
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
@@ -149,7 +152,7 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
       const float2 t1 = tw_mul<R, INV>(y1[kk], kk, R);
       const float2 t2 = tw_mul<R, INV>(y2[kk], 2 * kk, R);
       const float2 sum = cadd(t1, t2), dif = csub(t1, t2);
-      const float2 mid = make_float2(t0.x - 0.5f * sum.x, t0.y - 0.5f * sum.y);
+      const float2 mid = make_float2(fmaf(-0.5f, sum.x, t0.x), fmaf(-0.5f, sum.y, t0.y));
       const float2 rot = make_float2(-s3 * dif.y, s3 * dif.x);  // i * s3 * dif
       a[kk] = cadd(t0, sum);
       a[kk + M] = cadd(mid, rot);
@@ -243,6 +246,22 @@ __device__ __forceinline__ float2 lds_tw(const float2* tw, int e) {
   return INV ? w : make_float2(w.x, -w.y);
 }
 
+// Twiddle table views.  TS = 0: tw[e] = W^e for e in [0, n).  TS > 0:
+// tw[e TS] = W^e for e in [0, n/2) only (a strided column, e.g. the padding
+// column of a transpose buffer), and W^(e + n/2) = -W^e.  The table is
+// correctly rounded and W^(n/2) = -1, so both views give the same bits.
+template <bool INV, int n, int TS>
+__device__ __forceinline__ float2 tw_at(const float2* tw, int e) {
+  if constexpr (TS == 0) {
+    return lds_tw<INV>(tw, e);
+  } else {
+    const bool hi = e >= n / 2;
+    const float2 w = tw[(hi ? e - n / 2 : e) * TS];
+    const float c = hi ? -w.x : w.x, sn = hi ? -w.y : w.y;
+    return make_float2(c, INV ? sn : -sn);
+  }
+}
+
 // --------------------------------------------- cross-lane radix-8 (Q = 8)
 // The 8 lanes of a line are relabelled ql = q (q < 4), 11 - q (q >= 4), so
 // that the partner at logical distance 4 is the DPP row_half_mirror partner
@@ -299,12 +318,12 @@ __device__ __forceinline__ void xlane8_brev2nat(float2 (&a)[R], int ql) {
 
 // Line FFT over Q lanes, decimation in time.  In: logical lane ql holds
 // x[ql + Q p] in a[p].  Out: it holds X[R * brevq(ql) + k] in a[k].
-template <int n, bool INV, int Q = kQ>
+template <int n, bool INV, int Q = kQ, int TS = 0>
 __device__ __forceinline__ void line_dit(float2 (&a)[n / Q], int ql, const float2* tw) {
   constexpr int R = n / Q;
   fft_reg<R, INV>(a);
 #pragma unroll
-  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], lds_tw<INV>(tw, ql * k));
+  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw_at<INV, n, TS>(tw, ql * k));
   if constexpr (Q == 4)
     xlane_nat2brev<INV>(a, ql);
   else
@@ -312,7 +331,7 @@ __device__ __forceinline__ void line_dit(float2 (&a)[n / Q], int ql, const float
 }
 // Line FFT over Q lanes, decimation in frequency.  In: logical lane ql holds
 // x[R * brevq(ql) + m] in a[m].  Out: it holds X[ql + Q k] in a[k].
-template <int n, bool INV, int Q = kQ>
+template <int n, bool INV, int Q = kQ, int TS = 0>
 __device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float2* tw) {
   constexpr int R = n / Q;
   if constexpr (Q == 4)
@@ -320,7 +339,7 @@ __device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float
   else
     xlane8_brev2nat<INV>(a, ql);
 #pragma unroll
-  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], lds_tw<INV>(tw, ql * m));
+  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw_at<INV, n, TS>(tw, ql * m));
   fft_reg<R, INV>(a);
 }
 
@@ -637,6 +656,144 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
     }
     t.e_part[(size_t)it.iter * t.e_stride + it.led] = e;
     t.i_part[(size_t)it.iter * t.e_stride + it.led] = s;
+  }
+  };
+  if constexpr (SEQ) {
+    const int2 rg = ranges[blockIdx.x];
+    for (int ii = rg.x; ii < rg.x + rg.y; ++ii) {
+      run_item(ii);
+      lds_barrier();  // LDS and reductions are reused by the next member
+    }
+  } else {
+    run_item((int)blockIdx.x);
+  }
+}
+
+// Two-workgroups-per-CU form of the update: n Q / ROUNDS threads run the
+// lines of each phase in ROUNDS rounds (lines l, l + n/ROUNDS, ...), so a
+// workgroup holds half the waves and, with the twiddles in the padding column
+// of the transpose buffer (rows max(nd, n/2)), under half of the CU's LDS:
+// two updates share a CU and fill each other's barrier and memory waits.
+// Each line is transformed exactly as in update_kernel, so both give the
+// same bits.  A phase-B thread reads and writes only its own columns of its
+// own row, so the row transforms work in place without a barrier.
+template <int n, int PAD, int Q, int ROUNDS, bool SEQ>
+__global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void update_kernel_rounds(
+    const TileDev* __restrict__ tiles, const Item* __restrict__ items,
+    const int2* __restrict__ ranges) {
+  constexpr int R = n / Q;
+  constexpr int NT = n * Q / ROUNDS;
+  constexpr int LPR = NT / Q;  // lines per round
+  constexpr int NW = NT / 64;
+  constexpr int PT = pitch<n, PAD>();
+  static_assert(PAD >= 1 && LPR * ROUNDS == n && NT % 64 == 0, "layout");
+  extern __shared__ float2 sbuf[];  // [max(nd, n/2)][PT]; column n: twiddles
+  float2* const tw = sbuf + n;
+  __shared__ float red_pmax[NW];
+  // residual partials per (round, wave): the waves of update_kernel, in order
+  __shared__ double red_e[ROUNDS * NW], red_i[ROUNDS * NW];
+
+  auto run_item = [&](const int ii) {
+  const Item it = items[ii];
+  const TileDev t = tiles[it.tile];
+  const int mode = t.mode;
+  const int tid = threadIdx.x;
+  const int q_item = lane_log<Q>(tid % Q), l0 = tid / Q;
+  const int wave = tid >> 6;
+  const int N = t.N;
+  const int xc = R * brevq<Q>(q_item);
+  const size_t woff = (size_t)it.wy0 * N + it.wx0;
+  const __amdgpu_buffer_rsrc_t Sw = make_rsrc(t.S + woff, (unsigned)(((size_t)N * N - woff) * 8));
+  const __amdgpu_buffer_rsrc_t Pw = make_rsrc(t.P, n * n * 8);
+  const __amdgpu_buffer_rsrc_t Iw = make_rsrc(t.I + (size_t)it.led * n * n, n * n * 4);
+  const __amdgpu_buffer_rsrc_t Dw = make_rsrc(t.dP + (SEQ ? 0 : (size_t)it.slot * n * n), n * n * 8);
+  for (int e = tid; e < n / 2; e += NT) tw[e * PT] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
+  const float sigf = (float)*t.sigma;
+  float2 a[R];
+  lds_barrier();  // twiddles ready
+
+  // ---- phase A: support columns, IFFT along ky
+  float pm = 0.0f;
+#pragma unroll 1
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+    const int line = l0 + LPR * rd;
+    if (line < t.nd) {
+      const int q = opaque(q_item);
+      const int kx = t.kx0 + line;
+      pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
+      line_dit<n, true, Q, PT>(a, q, tw);
+      float2* dst = sbuf + line * PT + xc;
+#pragma unroll
+      for (int k = 0; k < R; ++k) dst[k] = a[k];
+    }
+  }
+  pm = wave_max(pm);
+  if ((tid & 63) == 0) red_pmax[wave] = pm;
+  lds_barrier();
+
+  // ---- phase B: rows, IFFT along kx, modulus, FFT along x, in place
+#pragma unroll 1
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+    const int line = l0 + LPR * rd;
+    const int q = opaque(q_item);
+    load_rows<n, PAD, Q>(sbuf, t.kx0, t.nd, line, q, a);
+    line_dit<n, true, Q, PT>(a, q, tw);
+    // the intensities are loaded after the transform (registers); the other
+    // workgroup on the CU covers the wait
+    float iv[R];
+#pragma unroll
+    for (int v = 0; v < R / 4; ++v) {
+      const v4f f = __builtin_amdgcn_raw_buffer_load_b128(Iw, (line * n + xc + 4 * v) * 4, 0, 0);
+      iv[4 * v] = f.x;
+      iv[4 * v + 1] = f.y;
+      iv[4 * v + 2] = f.z;
+      iv[4 * v + 3] = f.w;
+    }
+    float e_acc = 0.0f, i_acc = 0.0f;
+    modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
+    {
+      const double e = wave_sum((double)e_acc), s2 = wave_sum((double)i_acc);
+      if ((tid & 63) == 0) {
+        red_e[rd * NW + wave] = e;
+        red_i[rd * NW + wave] = s2;
+      }
+    }
+    line_dif<n, false, Q, PT>(a, q, tw);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int c = q + Q * k - t.kx0;
+      if (c >= 0 && c < t.nd) sbuf[c * PT + line] = a[k];
+    }
+  }
+  lds_barrier();
+
+  // ---- phase A': support columns, FFT along y, then the update
+  float pmax2 = red_pmax[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
+  const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
+#pragma unroll 1
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+    const int line = l0 + LPR * rd;
+    if (line < t.nd) {
+      const int q = opaque(q_item);
+      const float2* srcp = sbuf + line * PT + xc;
+#pragma unroll
+      for (int m = 0; m < R; ++m) a[m] = srcp[m];
+      line_dif<n, false, Q, PT>(a, q, tw);
+      const int kx = t.kx0 + line;
+      update_column<n, Q, SEQ>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, mode,
+                               it.slot, it.gsize);
+    }
+  }
+  if (tid == 0) {
+    double e = 0.0, s2 = 0.0;
+    for (int w = 0; w < ROUNDS * NW; ++w) {
+      e += red_e[w];
+      s2 += red_i[w];
+    }
+    t.e_part[(size_t)it.iter * t.e_stride + it.led] = e;
+    t.i_part[(size_t)it.iter * t.e_stride + it.led] = s2;
   }
   };
   if constexpr (SEQ) {
@@ -1023,7 +1180,7 @@ namespace {
 __device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2, bool inv) {
   const float s = inv ? 0.86602540378443864676f : -0.86602540378443864676f;
   const float2 t1 = cadd(a1, a2), t2 = csub(a1, a2);
-  const float2 m1 = make_float2(a0.x - 0.5f * t1.x, a0.y - 0.5f * t1.y);
+  const float2 m1 = make_float2(fmaf(-0.5f, t1.x, a0.x), fmaf(-0.5f, t1.y, a0.y));
   const float2 m2 = make_float2(-s * t2.y, s * t2.x);
   a0 = cadd(a0, t1);
   a1 = cadd(m1, m2);
@@ -1036,7 +1193,7 @@ __device__ __forceinline__ void dft5(float2 (&v)[5], bool inv) {
     for (int j = 1; j < 5; ++j) {
       const int e = (j * k) % 5;
       const float c = kTw<5>.c[e], s = inv ? kTw<5>.s[e] : -kTw<5>.s[e];
-      acc = cadd(acc, make_float2(v[j].x * c - v[j].y * s, v[j].x * s + v[j].y * c));
+      acc = cadd(acc, make_float2(fmaf(v[j].x, c, -(v[j].y * s)), fmaf(v[j].x, s, v[j].y * c)));
     }
     o[k] = acc;
   }
@@ -1198,6 +1355,20 @@ hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, 
   }
   return hipGetLastError();
 }
+template <int n, int PAD, int Q, int ROUNDS>
+hipError_t launch_update_rounds(const TileDev* tiles, const Item* items, int count, int nd_max,
+                                const int2* ranges, int nranges, hipStream_t st) {
+  // rows: the support columns, and at least n/2 for the twiddle column
+  const size_t lds = update_lds<n, PAD>(nd_max > n / 2 ? nd_max : n / 2);
+  if (ranges) {
+    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, true>), dim3(nranges),
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, ranges);
+  } else {
+    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, false>), dim3(count),
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, nullptr);
+  }
+  return hipGetLastError();
+}
 template <int n>
 hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
                            int variant, const int2* ranges, int nranges, hipStream_t st) {
@@ -1208,6 +1379,10 @@ hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, i
     case 3: return launch_update_np<n, 32, 4>(tiles, items, count, nd_max, ranges, nranges, st);
     case 4: return launch_update_np<n, 1, 8>(tiles, items, count, nd_max, ranges, nranges, st);
     case 5: return launch_update_np<n, 16, 8>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 6:
+      return launch_update_rounds<n, 1, 8, 2>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 7:
+      return launch_update_rounds<n, 1, 8, 4>(tiles, items, count, nd_max, ranges, nranges, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1244,6 +1419,14 @@ void set_lds_limit_n(int big) {
   (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 2, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 2, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 4, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 4, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)forward_kernel<n>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -223,8 +223,9 @@ def test_uneven_batch_matches_oracle(fpm, orc):
 
 @pytest.mark.parametrize("n", [64, 96, 128])
 def test_update_variants(fpm, orc, monkeypatch, n):
-    """The autotuner's variants: 4 or 8 lanes per line, LDS row padding.
-    Variants of one lane count differ only in padding and give the same bits;
+    """The autotuner's variants: 4 or 8 lanes per line, LDS row padding, one
+    or several rounds of lines per workgroup (6, 7: two and four rounds).
+    Variants of one lane count differ only in layout and give the same bits;
     the 8-lane form orders its floating-point steps differently and must meet
     the same tolerance against the oracle."""
     rng = np.random.default_rng(n)
@@ -239,7 +240,7 @@ def test_update_variants(fpm, orc, monkeypatch, n):
         Is.append(I)
     refs = [oracle_run(orc, d, I) for d, I in zip(descs, Is)]
     first = {}
-    for v in range(6):
+    for v in range(8):
         monkeypatch.setenv("FPM_UPDATE_VARIANT", str(v))
         _, out = run_gpu(fpm, descs, Is)
         fam = 4 if v < 4 else 8
