@@ -261,13 +261,16 @@ typedef struct {
   int32_t pad;
   int64_t items;      /* FPM_KERNEL_UPDATE: LED-tile updates processed      */
   double total_ms;    /* sum of per-launch durations (HIP events)           */
+  double busy_ms;     /* time at least one launch of this kind ran (the
+                         union of the launch intervals; chains overlap)    */
 } fpm_kernel_time;
 
 /* Run the reconstruction sweep of `plan` once, eagerly (no graph), with a
- * HIP event pair around every launch on `hip_stream`; synchronise; fill
- * out[FPM_KERNEL_KINDS].  Same kernels and launch shapes as
- * fpm_reconstruct; the state it leaves is that of a reconstruction.
- * `intensity` as in fpm_reconstruct with FPM_MEM_DEVICE. */
+ * HIP event pair around every launch on the stream it runs on (the chains
+ * of tiles concurrently, as in fpm_reconstruct, forked from and joined back
+ * into `hip_stream`); synchronise; fill out[FPM_KERNEL_KINDS].  Same kernels
+ * and launch shapes as fpm_reconstruct; the state it leaves is that of a
+ * reconstruction.  `intensity` as in fpm_reconstruct with FPM_MEM_DEVICE. */
 fpm_status fpm_profile_reconstruct(fpm_plan_t *plan, const float *intensity,
                                    fpm_kernel_time *out, void *hip_stream);
 

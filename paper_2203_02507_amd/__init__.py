@@ -75,7 +75,7 @@ class TileInfoC(C.Structure):
 
 class KernelTimeC(C.Structure):
     _fields_ = [("launches", C.c_int32), ("pad", C.c_int32), ("items", C.c_int64),
-                ("total_ms", C.c_double)]
+                ("total_ms", C.c_double), ("busy_ms", C.c_double)]
 
 
 KERNEL_KINDS = ("update", "pupil_mean", "iter_end", "spec_max", "init")
@@ -302,12 +302,15 @@ def fpm_online_abort(plan: Plan) -> int:
 
 
 def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:
-    """Per-kind kernel time of one eager reconstruction sweep (HIP events)."""
+    """Per-kind kernel time of one eager reconstruction sweep (HIP events
+    around every launch, chains concurrent): launches, items, summed launch
+    durations and the union of the launch intervals."""
     out = (KernelTimeC * len(KERNEL_KINDS))()
     check(lib.fpm_profile_reconstruct(plan.handle, _ptr(intensity, FPM_MEM_DEVICE), out,
                                       _stream(stream)))
     return {name: {"launches": out[i].launches, "items": out[i].items,
-                   "total_ms": out[i].total_ms} for i, name in enumerate(KERNEL_KINDS)}
+                   "total_ms": out[i].total_ms, "busy_ms": out[i].busy_ms}
+            for i, name in enumerate(KERNEL_KINDS)}
 
 
 def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where: int,

@@ -411,14 +411,17 @@ fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity
   ex.online_pushed[led] = 1;
   if (++ex.online_count == L) {
     // iteration 0 is complete: its residual, and the spectrum maximum the
-    // next iteration's pupil steps divide by
-    const size_t end0 = ex.iter_first_launch.size() > 1 ? (size_t)ex.iter_first_launch[1]
-                                                        : ex.launches.size();
-    for (size_t li = (size_t)ex.iter_first_launch[0]; li < end0; ++li) {
-      const Launch::Kind k = ex.launches[li].kind;
-      if ((k == Launch::ITER_END || k == Launch::SMAX) &&
-          !hip_ok(ex.enqueue_range(li, li + 1, s), "iteration end", &st))
-        return st;
+    // next iteration's pupil steps divide by (each chain's own launches)
+    for (size_t p = 0; p < ex.parts.size(); ++p) {
+      const std::vector<int>& first = ex.part_iter_first[p];
+      if (first.empty()) continue;
+      const size_t end0 = first.size() > 1 ? (size_t)first[1] : (size_t)ex.parts[p].second;
+      for (size_t li = (size_t)first[0]; li < end0; ++li) {
+        const Launch::Kind k = ex.launches[li].kind;
+        if ((k == Launch::ITER_END || k == Launch::SMAX) &&
+            !hip_ok(ex.enqueue_range(li, li + 1, s), "iteration end", &st))
+          return st;
+      }
     }
   }
   return FPM_OK;
@@ -438,11 +441,12 @@ fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, 
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_finish: cannot select the plan's device");
   hipStream_t s = (hipStream_t)hip_stream;
   fpm_status st = FPM_OK;
-  // iterations 1.. over the whole stack, in the plan's order
-  if (ex.iter_first_launch.size() > 1 &&
-      !hip_ok(ex.enqueue_range((size_t)ex.iter_first_launch[1], ex.launches.size(), s),
-              "remaining iterations", &st))
-    return st;
+  // iterations 1.. over the whole stack, in the plan's order, chain by chain
+  for (size_t p = 0; p < ex.parts.size(); ++p)
+    if (ex.part_iter_first[p].size() > 1 &&
+        !hip_ok(ex.enqueue_range((size_t)ex.part_iter_first[p][1], (size_t)ex.parts[p].second, s),
+                "remaining iterations", &st))
+      return st;
   ex.online_count = -1;
   st = collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
   // the plan's own first LED again for later fpm_reconstruct calls

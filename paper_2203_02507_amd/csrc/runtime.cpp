@@ -90,6 +90,11 @@ hipError_t DevBuf::alloc(size_t n) {
 Executor::~Executor() {
   if (graph_exec) hipGraphExecDestroy(graph_exec);
   if (cap_stream) hipStreamDestroy(cap_stream);
+  for (int p = 0; p < kMaxChains; ++p) {
+    if (chain_stream[p]) hipStreamDestroy(chain_stream[p]);
+    if (join_ev[p]) hipEventDestroy(join_ev[p]);
+  }
+  if (fork_ev) hipEventDestroy(fork_ev);
   if (online_ev) hipEventDestroy(online_ev);
   if (online_pin) hipHostFree(online_pin);
 }
@@ -191,7 +196,8 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
   }
   if (nclass.count(256) &&
-      !hip_ok(big_scratch.alloc(big_scratch_bytes(256)), "hipMalloc(transpose slots)", &st))
+      !hip_ok(big_scratch.alloc(kMaxChains * big_scratch_bytes(256)), "hipMalloc(transpose slots)",
+              &st))
     return st;
   std::map<std::pair<int, int>, std::pair<const uint16_t*, const uint16_t*>> utabs;
   for (auto& kv : uclass) {
@@ -220,176 +226,226 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     launches.push_back(l);
     init_ids = l;
   }
-  std::vector<int> prev_active;
-  int reuse_from = -1;  // first launch index of the previous iteration body
-  iter_first_launch.clear();
-  for (int k = 0; k < max_iter; ++k) {
-    std::vector<int> active;
-    for (int t = 0; t < T; ++t)
-      if (tiles[t].d.iterations > k && !piped(tiles[t])) active.push_back(t);
-    const int body_start = (int)launches.size();
-    iter_first_launch.push_back(body_start);
-    if (k > 0 && active == prev_active && reuse_from >= 0) {
-      // identical work lists: replay the previous iteration's launches
-      const int body_len = body_start - reuse_from;
-      for (int i = 0; i < body_len; ++i) {
-        Launch l = launches[reuse_from + i];
-        if (l.kind == Launch::ITER_END) l.iter = k;
-        if (l.kind == Launch::SMAX && k + 1 >= max_iter) {
-          bool any = false;
-          for (int t : active) any |= tiles[t].d.iterations > k + 1;
-          if (!any) continue;
+  // Chains: the tiles are split into independent launch sequences, balanced
+  // by update count, that run on streams of their own; one chain's partial
+  // last wave of workgroups and its short group-mean launches then overlap
+  // the other chain's updates.  A tile's own launches keep their order, so
+  // the results do not depend on the split.
+  int P = T >= 2 ? 2 : 1;
+  if (const char* v = std::getenv("FPM_CHAINS")) {
+    const int k = std::atoi(v);
+    if (k >= 1 && k <= kMaxChains) P = std::min(k, T);
+  }
+  std::vector<int> part_of(T, 0);
+  {
+    std::vector<int> ord(T);
+    for (int t = 0; t < T; ++t) ord[t] = t;
+    auto cost = [&](int t) {
+      return (double)tiles[t].L * tiles[t].d.iterations * tiles[t].n * tiles[t].n;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<double> load(P, 0.0);
+    for (int t : ord) {
+      const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      part_of[t] = q;
+      load[q] += cost(t);
+    }
+  }
+  parts.clear();
+  part_iter_first.assign(P, {});
+  for (int p = 0; p < P; ++p) {
+    float2* chain_scratch =
+        big_scratch.p ? (float2*)((char*)big_scratch.p + (size_t)p * big_scratch_bytes(256))
+                      : nullptr;
+    const int part_begin = (int)launches.size();
+    std::vector<int> prev_active;
+    int reuse_from = -1;  // first launch index of the previous iteration body
+    for (int k = 0; k < max_iter; ++k) {
+      std::vector<int> active;
+      for (int t = 0; t < T; ++t)
+        if (part_of[t] == p && tiles[t].d.iterations > k && !piped(tiles[t])) active.push_back(t);
+      const int body_start = (int)launches.size();
+      part_iter_first[p].push_back(body_start);
+      if (k > 0 && active == prev_active && reuse_from >= 0) {
+        // identical work lists: replay the previous iteration's launches
+        const int body_len = body_start - reuse_from;
+        for (int i = 0; i < body_len; ++i) {
+          Launch l = launches[reuse_from + i];
+          if (l.kind == Launch::ITER_END) l.iter = k;
+          if (l.kind == Launch::SMAX && k + 1 >= max_iter) {
+            bool any = false;
+            for (int t : active) any |= tiles[t].d.iterations > k + 1;
+            if (!any) continue;
+          }
+          launches.push_back(l);
         }
-        launches.push_back(l);
+        reuse_from = body_start;
+        prev_active = active;
+        continue;
+      }
+      for (int s = 0; s < max_steps; ++s) {
+        std::vector<char> seq_done(T, 0);  // tiles whose group mean runs inside the update
+        for (auto& kv : uclass) {
+          Launch l{};
+          l.kind = Launch::UPDATE;
+          l.n = kv.first.first;
+          l.prec = kv.first.second;
+          l.nd_max = kv.second.first;
+          l.box_max = kv.second.second;
+          if (l.n == 256) l.big_scratch = chain_scratch;
+          if (l.prec != FPM_PREC_FP32_FFT) {
+            l.tabE = utabs[kv.first].first;
+            l.tabF = utabs[kv.first].second;
+          }
+          l.off = (int)items.size();
+          for (int t : active) {
+            const TilePlan& tp = tiles[t];
+            if (tp.n != l.n || tp.d.precision != l.prec || s >= tp.nsteps) continue;
+            for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
+              const int j = tp.step_leds[m];
+              Item it{};
+              it.tile = t;
+              it.led = j;
+              it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+              it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+              it.slot = m - tp.step_beg[s];
+              it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
+              items.push_back(it);
+            }
+          }
+          l.count = (int)items.size() - l.off;
+          if (l.count > 0 && l.prec == FPM_PREC_FP32_FFT && l.n <= 128) {
+            // items of one tile are contiguous and in slot order
+            std::vector<int2> rg;
+            for (int i = l.off; i < l.off + l.count;) {
+              int j = i;
+              while (j < l.off + l.count && items[j].tile == items[i].tile) ++j;
+              rg.push_back(make_int2(i - l.off, j - i));
+              i = j;
+            }
+            if (use_group_seq((int)rg.size())) {
+              l.roff = (int)ranges.size();
+              l.rcount = (int)rg.size();
+              ranges.insert(ranges.end(), rg.begin(), rg.end());
+              for (const int2& r : rg) seq_done[items[l.off + r.x].tile] = 1;
+            }
+          }
+          if (l.count > 0) launches.push_back(l);
+        }
+        // pupil means of the groups that ran in this step
+        Launch r{};
+        r.kind = Launch::REDUCE;
+        r.off = (int)steptiles.size();
+        int nmax = 0;
+        for (int t : active) {
+          const TilePlan& tp = tiles[t];
+          if (host_tiles[t].mode != 2 || s >= tp.nsteps || seq_done[t]) continue;
+          steptiles.push_back(StepTile{t, tp.step_beg[s + 1] - tp.step_beg[s]});
+          nmax = std::max(nmax, tp.n);
+        }
+        r.count = (int)steptiles.size() - r.off;
+        r.n = nmax;
+        if (r.count > 0) launches.push_back(r);
+      }
+      if (!active.empty()) {
+        Launch e = id_range(active);
+        e.kind = Launch::ITER_END;
+        e.iter = k;
+        launches.push_back(e);
+      }
+      std::vector<int> next;
+      for (int t : active)
+        if (tiles[t].d.iterations > k + 1) next.push_back(t);
+      if (!next.empty()) {
+        Launch m = id_range(next);
+        m.kind = Launch::SMAX;
+        launches.push_back(m);
       }
       reuse_from = body_start;
       prev_active = active;
-      continue;
     }
-    for (int s = 0; s < max_steps; ++s) {
-      std::vector<char> seq_done(T, 0);  // tiles whose group mean runs inside the update
-      for (auto& kv : uclass) {
-        Launch l{};
-        l.kind = Launch::UPDATE;
-        l.n = kv.first.first;
-        l.prec = kv.first.second;
-        l.nd_max = kv.second.first;
-        l.box_max = kv.second.second;
-        if (l.n == 256) l.big_scratch = (float2*)big_scratch.p;
-        if (l.prec != FPM_PREC_FP32_FFT) {
-          l.tabE = utabs[kv.first].first;
-          l.tabF = utabs[kv.first].second;
-        }
-        l.off = (int)items.size();
-        for (int t : active) {
-          const TilePlan& tp = tiles[t];
-          if (tp.n != l.n || tp.d.precision != l.prec || s >= tp.nsteps) continue;
-          for (int m = tp.step_beg[s]; m < tp.step_beg[s + 1]; ++m) {
-            const int j = tp.step_leds[m];
-            Item it{};
-            it.tile = t;
-            it.led = j;
-            it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
-            it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
-            it.slot = m - tp.step_beg[s];
-            it.gsize = tp.step_beg[s + 1] - tp.step_beg[s];
-            items.push_back(it);
+    // pipelined tiles: their level programs, level g of every such tile in one
+    // launch per (n, precision) class, iteration ends where a program has them
+    {
+      int max_levels = 0;
+      for (int t = 0; t < T; ++t)
+        if (part_of[t] == p && piped(tiles[t]))
+          max_levels = std::max(max_levels, tiles[t].nlevels);
+      for (int g = 0; g < max_levels; ++g) {
+        for (auto& kv : uclass) {
+          Launch l{};
+          l.kind = Launch::UPDATE;
+          l.n = kv.first.first;
+          l.prec = kv.first.second;
+          l.nd_max = kv.second.first;
+          l.box_max = kv.second.second;
+          if (l.n == 256) l.big_scratch = chain_scratch;
+          if (l.prec != FPM_PREC_FP32_FFT) {
+            l.tabE = utabs[kv.first].first;
+            l.tabF = utabs[kv.first].second;
           }
-        }
-        l.count = (int)items.size() - l.off;
-        if (l.count > 0 && l.prec == FPM_PREC_FP32_FFT && l.n <= 128) {
-          // items of one tile are contiguous and in slot order
-          std::vector<int2> rg;
-          for (int i = l.off; i < l.off + l.count;) {
-            int j = i;
-            while (j < l.off + l.count && items[j].tile == items[i].tile) ++j;
-            rg.push_back(make_int2(i - l.off, j - i));
-            i = j;
+          l.off = (int)items.size();
+          for (int t = 0; t < T; ++t) {
+            const TilePlan& tp = tiles[t];
+            if (part_of[t] != p || !piped(tp) || tp.n != l.n || tp.d.precision != l.prec ||
+                g >= tp.nlevels)
+              continue;
+            const int b = tp.prog_beg[g], e = tp.prog_beg[g + 1];
+            for (int m = b; m < e; ++m) {
+              const int j = tp.prog_led[m];
+              Item it{};
+              it.tile = t;
+              it.led = j;
+              it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
+              it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
+              it.slot = m - b;
+              it.gsize = e - b;
+              it.iter = tp.prog_iter[m];
+              items.push_back(it);
+            }
           }
-          if (use_group_seq((int)rg.size())) {
-            l.roff = (int)ranges.size();
-            l.rcount = (int)rg.size();
-            ranges.insert(ranges.end(), rg.begin(), rg.end());
-            for (const int2& r : rg) seq_done[items[l.off + r.x].tile] = 1;
-          }
+          l.count = (int)items.size() - l.off;
+          if (l.count > 0) launches.push_back(l);
         }
-        if (l.count > 0) launches.push_back(l);
-      }
-      // pupil means of the groups that ran in this step
-      Launch r{};
-      r.kind = Launch::REDUCE;
-      r.off = (int)steptiles.size();
-      int nmax = 0;
-      for (int t : active) {
-        const TilePlan& tp = tiles[t];
-        if (host_tiles[t].mode != 2 || s >= tp.nsteps || seq_done[t]) continue;
-        steptiles.push_back(StepTile{t, tp.step_beg[s + 1] - tp.step_beg[s]});
-        nmax = std::max(nmax, tp.n);
-      }
-      r.count = (int)steptiles.size() - r.off;
-      r.n = nmax;
-      if (r.count > 0) launches.push_back(r);
-    }
-    if (!active.empty()) {
-      Launch e = id_range(active);
-      e.kind = Launch::ITER_END;
-      e.iter = k;
-      launches.push_back(e);
-    }
-    std::vector<int> next;
-    for (int t : active)
-      if (tiles[t].d.iterations > k + 1) next.push_back(t);
-    if (!next.empty()) {
-      Launch m = id_range(next);
-      m.kind = Launch::SMAX;
-      launches.push_back(m);
-    }
-    reuse_from = body_start;
-    prev_active = active;
-  }
-  // pipelined tiles: their level programs, level g of every such tile in one
-  // launch per (n, precision) class, iteration ends where a program has them
-  {
-    int max_levels = 0;
-    for (const TilePlan& tp : tiles)
-      if (piped(tp)) max_levels = std::max(max_levels, tp.nlevels);
-    for (int g = 0; g < max_levels; ++g) {
-      for (auto& kv : uclass) {
-        Launch l{};
-        l.kind = Launch::UPDATE;
-        l.n = kv.first.first;
-        l.prec = kv.first.second;
-        l.nd_max = kv.second.first;
-        l.box_max = kv.second.second;
-        if (l.n == 256) l.big_scratch = (float2*)big_scratch.p;
-        if (l.prec != FPM_PREC_FP32_FFT) {
-          l.tabE = utabs[kv.first].first;
-          l.tabF = utabs[kv.first].second;
-        }
-        l.off = (int)items.size();
+        std::map<int, std::vector<int>> ends;  // iteration -> tiles ending it after level g
         for (int t = 0; t < T; ++t) {
           const TilePlan& tp = tiles[t];
-          if (!piped(tp) || tp.n != l.n || tp.d.precision != l.prec || g >= tp.nlevels) continue;
-          const int b = tp.prog_beg[g], e = tp.prog_beg[g + 1];
-          for (int m = b; m < e; ++m) {
-            const int j = tp.prog_led[m];
-            Item it{};
-            it.tile = t;
-            it.led = j;
-            it.wy0 = tp.N / 2 + tp.off[2 * j] - tp.n / 2;
-            it.wx0 = tp.N / 2 + tp.off[2 * j + 1] - tp.n / 2;
-            it.slot = m - b;
-            it.gsize = e - b;
-            it.iter = tp.prog_iter[m];
-            items.push_back(it);
-          }
+          if (part_of[t] == p && piped(tp) && g < tp.nlevels && tp.prog_end[g] >= 0)
+            ends[tp.prog_end[g]].push_back(t);
         }
-        l.count = (int)items.size() - l.off;
-        if (l.count > 0) launches.push_back(l);
-      }
-      std::map<int, std::vector<int>> ends;  // iteration -> tiles ending it after level g
-      for (int t = 0; t < T; ++t) {
-        const TilePlan& tp = tiles[t];
-        if (piped(tp) && g < tp.nlevels && tp.prog_end[g] >= 0) ends[tp.prog_end[g]].push_back(t);
-      }
-      for (auto& kv : ends) {
-        Launch e = id_range(kv.second);
-        e.kind = Launch::ITER_END;
-        e.iter = kv.first;
-        launches.push_back(e);
-        std::vector<int> next;
-        for (int t : kv.second)
-          if (tiles[t].d.iterations > kv.first + 1) next.push_back(t);
-        if (!next.empty()) {
-          Launch m = id_range(next);
-          m.kind = Launch::SMAX;
-          launches.push_back(m);
+        for (auto& kv : ends) {
+          Launch e = id_range(kv.second);
+          e.kind = Launch::ITER_END;
+          e.iter = kv.first;
+          launches.push_back(e);
+          std::vector<int> next;
+          for (int t : kv.second)
+            if (tiles[t].d.iterations > kv.first + 1) next.push_back(t);
+          if (!next.empty()) {
+            Launch m = id_range(next);
+            m.kind = Launch::SMAX;
+            launches.push_back(m);
+          }
         }
       }
     }
+    parts.emplace_back(part_begin, (int)launches.size());
   }
   total_updates = 0;
   for (const TilePlan& tp : tiles) total_updates += (int64_t)tp.d.iterations * tp.L;
+  // the chains' streams and fork / join events, before any graph capture
+  if (parts.size() > 1 && !fork_ev &&
+      !hip_ok(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming), "hipEventCreate", &st))
+    return st;
+  for (size_t p = 1; p < parts.size(); ++p) {
+    if (!chain_stream[p] &&
+        !hip_ok(hipStreamCreateWithFlags(&chain_stream[p], hipStreamNonBlocking), "hipStreamCreate",
+                &st))
+      return st;
+    if (!join_ev[p] &&
+        !hip_ok(hipEventCreateWithFlags(&join_ev[p], hipEventDisableTiming), "hipEventCreate", &st))
+      return st;
+  }
 
   if (!hip_ok(items_d.alloc(std::max<size_t>(1, items.size()) * sizeof(Item)), "hipMalloc(items)",
               &st))
@@ -555,47 +611,87 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
 
 hipError_t Executor::profile(hipStream_t s, fpm_kernel_time* out) {
   for (int k = 0; k < FPM_KERNEL_KINDS; ++k) out[k] = fpm_kernel_time{};
-  std::vector<hipEvent_t> ev(2 * launches.size() + 2, nullptr);
+  const size_t nl = launches.size();
+  std::vector<hipEvent_t> ev(2 * nl, nullptr);
   hipError_t e = hipSuccess;
   for (auto& x : ev)
     if ((e = hipEventCreate(&x)) != hipSuccess) break;
-  std::vector<int> kinds;
-  std::vector<int64_t> nitems;
-  size_t used = 0;
-  if (e == hipSuccess) {
-    // one launch of the sweep at a time, bracketed by events
-    std::vector<Launch> saved = launches;
-    for (size_t i = 0; i < saved.size() && e == hipSuccess; ++i) {
-      launches.assign(1, saved[i]);
-      e = hipEventRecord(ev[used], s);
-      if (e == hipSuccess) e = enqueue_sweep(s);
-      if (e == hipSuccess) e = hipEventRecord(ev[used + 1], s);
-      used += 2;
-      const Launch& l = saved[i];
-      kinds.push_back(l.kind == Launch::UPDATE     ? FPM_KERNEL_UPDATE
-                      : l.kind == Launch::REDUCE   ? FPM_KERNEL_PUPIL_MEAN
-                      : l.kind == Launch::ITER_END ? FPM_KERNEL_ITER_END
-                      : l.kind == Launch::SMAX     ? FPM_KERNEL_SPEC_MAX
-                                                   : FPM_KERNEL_INIT);
-      nitems.push_back(l.kind == Launch::UPDATE ? l.count : 0);
-    }
-    launches = saved;
+  // launch i on its chain's stream, bracketed by events on that stream
+  auto timed = [&](size_t i, hipStream_t st) {
+    hipError_t r = hipEventRecord(ev[2 * i], st);
+    if (r == hipSuccess) r = enqueue_range(i, i + 1, st);
+    if (r == hipSuccess) r = hipEventRecord(ev[2 * i + 1], st);
+    return r;
+  };
+  if (e == hipSuccess && nl > 0) e = timed(0, s);  // initial state
+  if (e == hipSuccess && parts.size() > 1) e = hipEventRecord(fork_ev, s);
+  for (size_t p = 1; p < parts.size() && e == hipSuccess; ++p) {
+    e = hipStreamWaitEvent(chain_stream[p], fork_ev, 0);
+    for (int i = parts[p].first; i < parts[p].second && e == hipSuccess; ++i)
+      e = timed((size_t)i, chain_stream[p]);
+    if (e == hipSuccess) e = hipEventRecord(join_ev[p], chain_stream[p]);
   }
+  if (!parts.empty())
+    for (int i = parts[0].first; i < parts[0].second && e == hipSuccess; ++i) e = timed((size_t)i, s);
+  for (size_t p = 1; p < parts.size() && e == hipSuccess; ++p)
+    e = hipStreamWaitEvent(s, join_ev[p], 0);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  for (size_t i = 0; e == hipSuccess && i < kinds.size(); ++i) {
-    float ms = 0.0f;
-    e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
-    fpm_kernel_time& k = out[kinds[i]];
+  // intervals relative to the first event; per kind: count, items, summed
+  // durations and the union of the intervals
+  std::vector<std::vector<std::pair<float, float>>> iv(FPM_KERNEL_KINDS);
+  for (size_t i = 0; e == hipSuccess && i < nl; ++i) {
+    float t0 = 0.0f, t1 = 0.0f;
+    e = hipEventElapsedTime(&t0, ev[0], ev[2 * i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[0], ev[2 * i + 1]);
+    if (e != hipSuccess) break;
+    const Launch& l = launches[i];
+    const int kind = l.kind == Launch::UPDATE     ? FPM_KERNEL_UPDATE
+                     : l.kind == Launch::REDUCE   ? FPM_KERNEL_PUPIL_MEAN
+                     : l.kind == Launch::ITER_END ? FPM_KERNEL_ITER_END
+                     : l.kind == Launch::SMAX     ? FPM_KERNEL_SPEC_MAX
+                                                  : FPM_KERNEL_INIT;
+    fpm_kernel_time& k = out[kind];
     k.launches += 1;
-    k.items += nitems[i];
-    k.total_ms += ms;
+    k.items += l.kind == Launch::UPDATE ? l.count : 0;
+    k.total_ms += t1 - t0;
+    iv[kind].emplace_back(t0, t1);
+  }
+  for (int k = 0; e == hipSuccess && k < FPM_KERNEL_KINDS; ++k) {
+    std::sort(iv[k].begin(), iv[k].end());
+    double busy = 0.0, lo = 0.0, hi = -1.0;
+    for (const auto& x : iv[k]) {
+      if (x.first > hi) {
+        if (hi > lo) busy += hi - lo;
+        lo = x.first;
+        hi = x.second;
+      } else if (x.second > hi) {
+        hi = x.second;
+      }
+    }
+    if (hi > lo) busy += hi - lo;
+    out[k].busy_ms = busy;
   }
   for (auto& x : ev)
     if (x) (void)hipEventDestroy(x);
   return e;
 }
 
-hipError_t Executor::enqueue_sweep(hipStream_t s) { return enqueue_range(0, launches.size(), s); }
+hipError_t Executor::enqueue_sweep(hipStream_t s) {
+  hipError_t e = enqueue_range(0, 1, s);  // initial state of every tile
+  if (e != hipSuccess || parts.empty()) return e;
+  if (parts.size() == 1) return enqueue_range(parts[0].first, parts[0].second, s);
+  if ((e = hipEventRecord(fork_ev, s)) != hipSuccess) return e;
+  for (size_t p = 1; p < parts.size(); ++p) {
+    if ((e = hipStreamWaitEvent(chain_stream[p], fork_ev, 0)) != hipSuccess ||
+        (e = enqueue_range(parts[p].first, parts[p].second, chain_stream[p])) != hipSuccess ||
+        (e = hipEventRecord(join_ev[p], chain_stream[p])) != hipSuccess)
+      return e;
+  }
+  if ((e = enqueue_range(parts[0].first, parts[0].second, s)) != hipSuccess) return e;
+  for (size_t p = 1; p < parts.size(); ++p)
+    if ((e = hipStreamWaitEvent(s, join_ev[p], 0)) != hipSuccess) return e;
+  return hipSuccess;
+}
 
 hipError_t Executor::enqueue_range(size_t begin, size_t end, hipStream_t s) {
   const TileDev* tab = (const TileDev*)table.p;

@@ -50,6 +50,9 @@ int update_variant(int n);
 void set_update_variant(int n, int v);
 bool update_variant_known(int n);
 
+// independent launch sequences (chains of tiles) of one plan
+constexpr int kMaxChains = 4;
+
 struct LineLaunch {
   int off = 0, count = 0, len = 0, max_lines = 0, inverse = 0;
 };
@@ -84,8 +87,13 @@ struct Executor {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
 
-  // first launch of each iteration of the iteration-aligned sweep
-  std::vector<int> iter_first_launch;
+  // launches[0] initialises every tile; chain p (tiles of its own, on a
+  // stream of its own) runs launches [parts[p].first, parts[p].second), and
+  // part_iter_first[p][k] is its first launch of iteration k
+  std::vector<std::pair<int, int>> parts;
+  std::vector<std::vector<int>> part_iter_first;
+  hipStream_t chain_stream[kMaxChains] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kMaxChains] = {};
   // online reconstruction (one LED's images at a time): the stack the pushes
   // fill, per-(LED, class) update launches of iteration 0 over every tile
   DevBuf online_I, online_items_d, online_src_off_d, online_stage;
@@ -101,6 +109,8 @@ struct Executor {
 
   ~Executor();
   fpm_status setup(const std::vector<TilePlan>& tiles);
+  // the whole sweep: initialisation on `s`, then the chains on their streams
+  // (forked from and joined back into `s`; also under graph capture)
   hipError_t enqueue_sweep(hipStream_t s);
   // launches [begin, end) of the sweep, eagerly
   hipError_t enqueue_range(size_t begin, size_t end, hipStream_t s);
