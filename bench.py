@@ -474,6 +474,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-online", action="store_true")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-tile latency section")
     ap.add_argument("--precisions", default="1,2",
                     help="MFMA precision variants timed beside the FP32 path (comma list, "
                          "empty for none)")
@@ -614,8 +616,10 @@ def main():
     for td in tds:
         td.desc.precision = 0
 
-    single = single_tile_bench(fpm)
-    log("single tile: " + json.dumps(single))
+    single = None
+    if not args.no_single:
+        single = single_tile_bench(fpm)
+        log("single tile: " + json.dumps(single))
 
     online = None
     if not args.no_online:
