@@ -195,8 +195,15 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     u.first = std::max(u.first, tp.nd);
     u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
   }
+  // number of chains of tiles (see below)
+  int P = T >= 2 ? 2 : 1;
+  if (const char* v = std::getenv("FPM_CHAINS")) {
+    const int k = std::atoi(v);
+    if (k >= 1 && k <= kMaxChains) P = std::min(k, T);
+  }
+  // transpose slots of the n = 256 kernels, one set per chain (chains run concurrently)
   if (nclass.count(256) &&
-      !hip_ok(big_scratch.alloc(kMaxChains * big_scratch_bytes(256)), "hipMalloc(transpose slots)",
+      !hip_ok(big_scratch.alloc((size_t)P * big_scratch_bytes(256)), "hipMalloc(transpose slots)",
               &st))
     return st;
   std::map<std::pair<int, int>, std::pair<const uint16_t*, const uint16_t*>> utabs;
@@ -231,11 +238,6 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
   // last wave of workgroups and its short group-mean launches then overlap
   // the other chain's updates.  A tile's own launches keep their order, so
   // the results do not depend on the split.
-  int P = T >= 2 ? 2 : 1;
-  if (const char* v = std::getenv("FPM_CHAINS")) {
-    const int k = std::atoi(v);
-    if (k >= 1 && k <= kMaxChains) P = std::min(k, T);
-  }
   std::vector<int> part_of(T, 0);
   {
     std::vector<int> ord(T);
