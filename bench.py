@@ -11,7 +11,8 @@ intensity stack already resident in HBM.
 
 Inputs are synthetic and seeded (fpm_synth): per-tile objects, the forward
 model run by the library itself, Poisson noise at 1e4 peak photons drawn
-with a seeded torch generator on the device.
+with a seeded torch generator on the device.  The tiles compared with the
+FP64 oracle get their stacks from the oracle's own forward model instead.
 
 Prints one JSON line (rank 0): metric, value, roofline of the update kernel
 (HIP events per launch), the FP64 CPU oracle timed on a bounded sample.
@@ -121,21 +122,41 @@ def mfma_flops_per_update(desc, prec):
     return steps * 4 * 2 * 32 * 32 * 16 * PREC_TERMS[prec], dense * PREC_TERMS[prec]
 
 
-def oracle_objects(tds, I, plan, tiles):
-    """FP64 oracle reconstructions of sampled tiles on the same noisy data."""
+def oracle_stacks(tds, tiles, plan, I, tiles_per_side, iterations):
+    """Intensity stacks of the sampled tiles from the FP64 oracle's forward
+    model (the tiles' own objects, defocus and shot noise, drawn again from
+    their seeds), written over those tiles' stacks in the device buffer, so
+    that the sampled tiles' inputs do not come from the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    import fpm_synth
+    import oracle
+
+    fresh = fpm_synth.full_fov_tiles(tiles_per_side=tiles_per_side, iterations=iterations,
+                                     only=tiles)
+    with ThreadPoolExecutor(len(tiles)) as ex:
+        stacks = list(ex.map(lambda td: oracle.synthesize(td, z_range=20.0)[2], fresh))
+    for t, td, st in zip(tiles, fresh, stacks):
+        assert td.desc.defocus_um == tds[t].desc.defocus_um  # the same draw
+        info = plan.infos[t]
+        sl = I[info.intensity_offset:info.intensity_offset + info.L * info.n * info.n]
+        sl.copy_(torch.from_numpy(st.reshape(-1)))
+    torch.cuda.synchronize()
+    return [td.desc for td in fresh], stacks
+
+
+def oracle_objects(descs, stacks):
+    """FP64 oracle reconstructions of the sampled tiles, one per thread."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
 
-    def one(t):
-        info = plan.infos[t]
-        Ih = I[info.intensity_offset:info.intensity_offset + info.L * info.n * info.n]
-        Ih = Ih.cpu().numpy().reshape(info.L, info.n, info.n)
-        r = oracle.reconstruct(tds[t].desc, Ih)
+    def one(a):
+        r = oracle.reconstruct(a[0], a[1])
         assert r.status == 0
-        return oracle.spectrum_to_object(tds[t].desc, r.S)
+        return oracle.spectrum_to_object(a[0], r.S)
 
-    with ThreadPoolExecutor(len(tiles)) as ex:
-        return list(ex.map(one, tiles))
+    with ThreadPoolExecutor(len(descs)) as ex:
+        return list(ex.map(one, zip(descs, stacks)))
 
 
 def sample_errors(plan, obj, tiles, refs):
@@ -507,6 +528,13 @@ def main():
         f"{I.numel() * 4 / 2**30:.2f} GiB of intensities on the device")
     obj, pup, res = fpm.device_buffers(plan, device)
     updates = sum(i.L * i.iterations for i in plan.infos)
+    sample = [int(x) for x in args.oracle_tiles.split(",") if x.strip()]
+    sample = [t for t in sample if t < plan.ntiles]
+    if sample:
+        t1 = time.perf_counter()
+        sample_descs, sample_stacks = oracle_stacks(tds, sample, plan, I, args.tiles_per_side,
+                                                    args.iterations)
+        log(f"oracle inputs for tiles {sample}: {time.perf_counter() - t1:.1f} s")
 
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
@@ -563,13 +591,11 @@ def main():
         del fov
         log("stitch: " + json.dumps(stitch))
 
-    sample = [int(x) for x in args.oracle_tiles.split(",") if x.strip()]
-    sample = [t for t in sample if t < plan.ntiles]
     refs = None
     errs = {}
     if sample:
         t1 = time.perf_counter()
-        refs = oracle_objects(tds, I, plan, sample)
+        refs = oracle_objects(sample_descs, sample_stacks)
         log(f"oracle on tiles {sample}: {time.perf_counter() - t1:.1f} s")
         errs["fp32_fft"] = sample_errors(plan, obj, sample, refs)
 
