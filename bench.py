@@ -306,6 +306,61 @@ def online_bench(fpm, tds, I, tiles_per_side: int, counts=(16, 256)):
     return out
 
 
+def paper_workload_bench(fpm, reps: int = 3):
+    """The paper's own GPU timing workload, as context: 169 LR images (13 x 13
+    LEDs, 2.5 mm pitch, 83 mm high, NA 0.1, 2.4 um camera pixels behind a 2x
+    objective), 16 sub-regions of 256 x 256 px (26 px overlap), one iteration.
+    The paper does not state the wavelength or the upsampling: 0.532 um and 4x
+    here.  Synthetic seeded objects and defocus, library forward model,
+    Poisson noise; sequential NA-order sweep and LED groups, mean of `reps`
+    runs (HIP events)."""
+    import numpy as np
+    import torch
+    import fpm_synth
+
+    rng = np.random.default_rng(2203)
+    stride, pix = 256 - 26, 1.2
+    descs = []
+    for ty in range(4):
+        for tx in range(4):
+            descs.append(fpm_synth.TileDesc(
+                n=256, upsample=4, led_rows=13, led_cols=13, led_pitch_um=2500.0,
+                led_height_um=83000.0, pixel_um=pix, na_obj=0.1, iterations=1,
+                tile_x_um=(tx - 1.5) * stride * pix, tile_y_um=(ty - 1.5) * stride * pix,
+                defocus_um=float(rng.uniform(-20, 20))))
+    out = {}
+    for name, sched in (("sequential", fpm.FPM_SCHED_SEQUENTIAL),
+                        ("led_groups", fpm.FPM_SCHED_LED_GROUPS)):
+        for d in descs:
+            d.schedule = sched
+        plan = fpm.Plan(descs)
+        objs = [fpm_synth.random_object(rng, d.N).astype(np.complex64) for d in descs]
+        o = torch.from_numpy(np.concatenate([x.reshape(-1) for x in objs]).view(np.float32)).cuda()
+        I = torch.empty(plan.total_intensity, dtype=torch.float32, device="cuda")
+        fpm.fpm_forward(plan, o, None, I, fpm.FPM_MEM_DEVICE)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(fpm_synth.ROOT_SEED)
+        I = torch.poisson(I.clamp_min(0) * (1e4 / float(I.max())), generator=gen) * (
+            float(I.max()) / 1e4)
+        ob, pu, re = fpm.device_buffers(plan)
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, ob, pu, re)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, ob, pu, re)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 3), "updates": 16 * 169,
+                     "updates_per_s": round(16 * 169 / (ms / 1e3), 1)}
+        del plan, o, I, ob, pu, re
+    out["paper_gpu_context"] = ("GTX 1050 laptop GPU, PyTorch: about 1.0 s for one sub-region "
+                                "and 0.9 s per further one (Sec. 4.1), i.e. about 14.5 s for 16; "
+                                "0.1 s per LR image for 16 sub-regions online (Sec. 3.4)")
+    return out
+
+
 def uneven_objects(tds, device):
     """Seeded objects of every tile (host threads), packed on the device."""
     from concurrent.futures import ThreadPoolExecutor
@@ -404,12 +459,12 @@ def uneven_bench(fpm, T: int, steps: int, warmup: int, sample: int = 16):
                               "speedup": round(ms_single / ms_batched, 2)}}
 
 
-def serving_bench(fpm, n_req: int = 48, load: float = 0.8, seed: int = 5):
+def serving_bench(fpm, n_req: int = 48, loads=(0.5, 0.8, 0.95), seed: int = 5):
     """Requests shaped like single uneven tiles (64-256 px, 9x9..21x21 LEDs,
     5..30 iterations; precision flags 50 % FP32, 25 % BF16x3, 25 % FP16 on
-    the sizes the MFMA form runs) arriving as a Poisson stream at `load` x the
-    saturated request rate measured closed-loop; p50/p99 latency and
-    sustained updates/s."""
+    the sizes the MFMA form runs) arriving as a Poisson stream at each of
+    `loads` x the saturated request rate measured closed-loop; p50/p99
+    latency and sustained updates/s per load."""
     import numpy as np
     import torch
     import fpm_synth
@@ -451,33 +506,38 @@ def serving_bench(fpm, n_req: int = 48, load: float = 0.8, seed: int = 5):
         srv.wait(i, d)
     t_sat = time.perf_counter() - t0
     srv.close()
-    rate = load * len(reqs) / t_sat
-    # open loop: Poisson arrivals at `rate`
-    rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, size=len(reqs))
-    srv = fpm.Server(budget, max_slots=256)
-    start = time.perf_counter()
-    due = start
-    ids = []
-    for (d, I), g in zip(reqs, gaps):
-        due += g
-        while time.perf_counter() < due:
-            time.sleep(min(1e-3, max(0.0, due - time.perf_counter())))
-        ids.append(srv.submit(d, I, fpm.FPM_MEM_DEVICE))
-    lat, first, last, upd = [], None, None, 0
-    for i, (d, _) in zip(ids, reqs):
-        _, st = srv.wait(i, d)
-        lat.append(st.finish_s - st.submit_s)
-        first = st.submit_s if first is None else min(first, st.submit_s)
-        last = st.finish_s if last is None else max(last, st.finish_s)
-        upd += st.updates
-    srv.close()
-    lat = np.array(lat)
-    return {"requests": len(reqs), "load": load, "arrival_rate_per_s": round(rate, 2),
-            "saturated_updates_per_s": round(sum(d.L * d.iterations for d, _ in reqs) / t_sat, 1),
+    sat_updates = sum(d.L * d.iterations for d, _ in reqs) / t_sat
+    by_load = {}
+    for ld in loads:
+        rate = ld * len(reqs) / t_sat
+        # open loop: Poisson arrivals at `rate`
+        rng = np.random.default_rng(seed)
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        srv = fpm.Server(budget, max_slots=256)
+        start = time.perf_counter()
+        due = start
+        ids = []
+        for (d, I), g in zip(reqs, gaps):
+            due += g
+            while time.perf_counter() < due:
+                time.sleep(min(1e-3, max(0.0, due - time.perf_counter())))
+            ids.append(srv.submit(d, I, fpm.FPM_MEM_DEVICE))
+        lat, first, last, upd = [], None, None, 0
+        for i, (d, _) in zip(ids, reqs):
+            _, st = srv.wait(i, d)
+            lat.append(st.finish_s - st.submit_s)
+            first = st.submit_s if first is None else min(first, st.submit_s)
+            last = st.finish_s if last is None else max(last, st.finish_s)
+            upd += st.updates
+        srv.close()
+        lat = np.array(lat)
+        by_load[str(ld)] = {
+            "arrival_rate_per_s": round(rate, 2),
             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-            "sustained_updates_per_s": round(upd / (last - first), 1),
+            "sustained_updates_per_s": round(upd / (last - first), 1)}
+    return {"requests": len(reqs), "saturated_updates_per_s": round(sat_updates, 1),
+            "by_load": by_load,
             "mix": "64-256 px tiles, 81-441 LEDs, 5-30 iterations, precision 50 % FP32, "
                    "25 % BF16x3, 25 % FP16 (FP32 for 256 px)",
             "precisions": {str(p): sum(1 for d, _ in reqs if d.precision == p)
@@ -647,6 +707,11 @@ def main():
         single = single_tile_bench(fpm)
         log("single tile: " + json.dumps(single))
 
+    paper = None
+    if not args.no_single:
+        paper = paper_workload_bench(fpm)
+        log("paper workload: " + json.dumps(paper))
+
     online = None
     if not args.no_online:
         online = online_bench(fpm, tds, I, args.tiles_per_side)
@@ -693,6 +758,7 @@ def main():
         "stitch": stitch,
         "single_tile": single,
         "online": online,
+        "paper_workload": paper,
         "uneven_batch": uneven,
         "serving": serving,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
