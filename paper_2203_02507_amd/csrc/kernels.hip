@@ -268,15 +268,23 @@ __device__ __forceinline__ float2 tw_at(const float2* tw, int e) {
 // (lane i <-> 7 - i), while logical distances 2 and 1 stay the quad
 // permutes xor 2 and xor 1.
 constexpr int kMirror8 = 0x141;
+// Q = 16: physical lane p of a row of 16 is relabelled ql = p ^ g(p3, p2)
+// with g = 0, 3, 4, 7 for (p3, p2) = 00, 01, 10, 11; then the DPP
+// row_mirror partner (15 - p) is at logical distance 8, the row_half_mirror
+// partner (p ^ 7) at distance 4, and the quad permutes xor 2 / xor 1 at
+// distances 2 / 1.  For p < 8 this is the Q = 8 relabelling.
+constexpr int kMirror16 = 0x140;
 template <int Q>
 __device__ __forceinline__ int lane_log(int q) {
   if constexpr (Q == 4) return q;
-  return q < 4 ? q : 11 - q;
+  if constexpr (Q == 8) return q < 4 ? q : 11 - q;
+  return q ^ ((q & 8) ? ((q & 4) ? 7 : 4) : ((q & 4) ? 3 : 0));
 }
 template <int Q>
 __device__ __forceinline__ int brevq(int ql) {
   if constexpr (Q == 4) return ((ql & 1) << 1) | ((ql >> 1) & 1);
-  return ((ql & 1) << 2) | (ql & 2) | ((ql >> 2) & 1);
+  if constexpr (Q == 8) return ((ql & 1) << 2) | (ql & 2) | ((ql >> 2) & 1);
+  return ((ql & 1) << 3) | ((ql & 2) << 1) | ((ql >> 1) & 2) | ((ql >> 3) & 1);
 }
 // W_8^j, j = 0..3 (INV: exp(+2 pi i j / 8), else exp(-2 pi i j / 8))
 template <bool INV>
@@ -316,6 +324,41 @@ __device__ __forceinline__ void xlane8_brev2nat(float2 (&a)[R], int ql) {
   }
 }
 
+// 16-point DFT across the lanes of a line, decimation in frequency: input
+// natural, output bit-reversed (X_{brev4(ql)}).  The W16 twiddle of the upper
+// half comes from the line's LDS table: W16^j = W_n^(j n / 16).
+template <int n, bool INV, int R, int TS>
+__device__ __forceinline__ void xlane16_nat2brev(float2 (&a)[R], int ql, const float2* tw) {
+  const float s8 = (ql & 8) ? -1.0f : 1.0f, s4 = (ql & 4) ? -1.0f : 1.0f,
+              s2 = (ql & 2) ? -1.0f : 1.0f, s1 = (ql & 1) ? -1.0f : 1.0f;
+  const float2 t16 = tw_at<INV, n, TS>(tw, (ql & 8) ? (ql & 7) * (n / 16) : 0);
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    float2 v = cmul(xstage<kMirror16>(a[i], s8), t16);
+    v = cmul(xstage<kMirror8>(v, s4), t8);
+    v = w4_lane3<INV>(xstage<kXor2>(v, s2), is3);
+    a[i] = xstage<kXor1>(v, s1);
+  }
+}
+// decimation in time: input bit-reversed, output natural
+template <int n, bool INV, int R, int TS>
+__device__ __forceinline__ void xlane16_brev2nat(float2 (&a)[R], int ql, const float2* tw) {
+  const float s8 = (ql & 8) ? -1.0f : 1.0f, s4 = (ql & 4) ? -1.0f : 1.0f,
+              s2 = (ql & 2) ? -1.0f : 1.0f, s1 = (ql & 1) ? -1.0f : 1.0f;
+  const float2 t16 = tw_at<INV, n, TS>(tw, (ql & 8) ? (ql & 7) * (n / 16) : 0);
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    float2 v = w4_lane3<INV>(xstage<kXor1>(a[i], s1), is3);
+    v = cmul(xstage<kXor2>(v, s2), t8);
+    v = cmul(xstage<kMirror8>(v, s4), t16);
+    a[i] = xstage<kMirror16>(v, s8);
+  }
+}
+
 // Line FFT over Q lanes, decimation in time.  In: logical lane ql holds
 // x[ql + Q p] in a[p].  Out: it holds X[R * brevq(ql) + k] in a[k].
 template <int n, bool INV, int Q = kQ, int TS = 0>
@@ -326,8 +369,10 @@ __device__ __forceinline__ void line_dit(float2 (&a)[n / Q], int ql, const float
   for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw_at<INV, n, TS>(tw, ql * k));
   if constexpr (Q == 4)
     xlane_nat2brev<INV>(a, ql);
-  else
+  else if constexpr (Q == 8)
     xlane8_nat2brev<INV>(a, ql);
+  else
+    xlane16_nat2brev<n, INV, R, TS>(a, ql, tw);
 }
 // Line FFT over Q lanes, decimation in frequency.  In: logical lane ql holds
 // x[R * brevq(ql) + m] in a[m].  Out: it holds X[ql + Q k] in a[k].
@@ -336,8 +381,10 @@ __device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float
   constexpr int R = n / Q;
   if constexpr (Q == 4)
     xlane_brev2nat<INV>(a, ql);
-  else
+  else if constexpr (Q == 8)
     xlane8_brev2nat<INV>(a, ql);
+  else
+    xlane16_brev2nat<n, INV, R, TS>(a, ql, tw);
 #pragma unroll
   for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw_at<INV, n, TS>(tw, ql * m));
   fft_reg<R, INV>(a);
@@ -851,16 +898,17 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 
 // ============================== sides whose transposes exceed LDS (n = 256)
 // Persistent form of the update: 512 threads run the lines of each phase in
-// Q n/512 rounds (Q = 8 lanes per line, R = n/8 points per lane), the two transposes go
-// through this workgroup's own slot of global scratch ([nd][n] complex, the
-// same layout as the LDS buffer), and each workgroup loops over items
-// blockIdx.x, blockIdx.x + gridDim.x, ...  Phase B writes the support
-// columns of its rows back into the slot in place: a thread reads and writes
-// only columns of one residue mod 4 of its own row, so no other thread's
-// input is overwritten.
+// Q n/512 rounds (Q = 16 lanes per line and R = n/16 points per lane by
+// default, which needs no register spills; Q = 8, R = n/8 also exists), the
+// two transposes go through this workgroup's own slot of global scratch
+// ([nd][n] complex, the same layout as the LDS buffer), and each workgroup
+// loops over items blockIdx.x, blockIdx.x + gridDim.x, ...  Phase B writes
+// the support columns of its rows back into the slot in place: a thread
+// reads and writes only its own columns (one residue mod Q) of its own row,
+// so no other thread's input is overwritten.
 constexpr int kBigThreads = 512;
 
-template <int n, int Q = 8>
+template <int n, int Q>
 __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
                                                                  const Item* __restrict__ items,
                                                                  int count,
@@ -1450,9 +1498,14 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
   set_lds_limits();
   if (n == 256) {
     if (!big_scratch) return hipErrorInvalidValue;
+    // 16 lanes per line (R = 16: no spills); odd variants: 8 lanes (R = 32)
     const int grid = count < kBigSlots ? count : kBigSlots;
-    hipLaunchKernelGGL(update_kernel_big<256>, dim3(grid), dim3(kBigThreads), 0, st, tiles, items,
-                       count, big_scratch);
+    if (variant & 1)
+      hipLaunchKernelGGL((update_kernel_big<256, 8>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
+                         items, count, big_scratch);
+    else
+      hipLaunchKernelGGL((update_kernel_big<256, 16>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
+                         items, count, big_scratch);
     return hipGetLastError();
   }
   switch (n) {
