@@ -734,6 +734,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   constexpr int NW = NT / 64;
   constexpr int PT = pitch<n, PAD>();
   static_assert(PAD >= 1 && LPR * ROUNDS == n && NT % 64 == 0, "layout");
+  static_assert(R % 4 == 0, "intensities are read four at a time");
   extern __shared__ float2 sbuf[];  // [max(nd, n/2)][PT]; column n: twiddles
   float2* const tw = sbuf + n;
   __shared__ float red_pmax[NW];
