@@ -729,7 +729,7 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     info = plan.infos[0]
     out = {
-        "metric": "LED-tile updates/sec (FP32 FFT path)",
+        "metric": "LED-tile updates/sec (FP32 vs MFMA DFT) + p50/p99 request latency",
         "value": round(value, 1),
         "unit": "updates/s",
         "n_gpus": 1,
