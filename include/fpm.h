@@ -202,8 +202,9 @@ fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem whe
  * (FPM_E_ARG otherwise).
  *   fpm_online_begin: opens a session on `plan` (device state, tuning and
  *     the first-iteration work lists are set up here, not in the pushes).
- *     While it is open, fpm_reconstruct and fpm_profile_reconstruct on the
- *     plan return FPM_E_STATE; begin again restarts the session.
+ *     While it is open, fpm_forward, fpm_reconstruct and
+ *     fpm_profile_reconstruct on the plan return FPM_E_STATE; begin again
+ *     restarts the session.
  *   fpm_online_push: `intensity` float [tile][n][n], the tiles' images for
  *     LED `led` (grid index), in plan tile order (each tile its own n).
  *     Each LED once, any order (FPM_E_ARG for a repeat or out of range).  The

@@ -245,6 +245,8 @@ fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, 
   if (!plan || !object || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_forward: NULL argument or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
+  if (plan->exec.online_count >= 0)
+    return fail(FPM_E_STATE, "fpm_forward: an online session holds the plan");
   DeviceGuard g(plan);
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_forward: cannot select the plan's device");
   fpm_status st = ensure_setup(plan);

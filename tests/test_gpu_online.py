@@ -178,6 +178,10 @@ def test_online_call_order_errors(fpm, orc):
     with pytest.raises(fpm.FpmError) as e:
         fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_HOST)
     assert e.value.status == fpm.FPM_E_STATE
+    with pytest.raises(fpm.FpmError) as e:
+        fpm.fpm_forward(plan, np.zeros(plan.total_object * 2, np.float32), None,
+                        np.zeros(plan.total_intensity, np.float32), fpm.FPM_MEM_HOST)
+    assert e.value.status == fpm.FPM_E_STATE
     fpm.fpm_online_abort(plan)
     obj = np.zeros(plan.total_object * 2, np.float32)
     pup = np.zeros(plan.total_pupil * 2, np.float32)
