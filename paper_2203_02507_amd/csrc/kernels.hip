@@ -1499,9 +1499,9 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
   set_lds_limits();
   if (n == 256) {
     if (!big_scratch) return hipErrorInvalidValue;
-    // 16 lanes per line (R = 16: no spills); odd variants: 8 lanes (R = 32)
+    // 16 lanes per line (R = 16: no spills); variant 1: 8 lanes (R = 32)
     const int grid = count < kBigSlots ? count : kBigSlots;
-    if (variant & 1)
+    if (variant == 1)
       hipLaunchKernelGGL((update_kernel_big<256, 8>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);
     else

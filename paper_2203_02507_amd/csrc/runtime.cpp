@@ -42,7 +42,7 @@ int update_variant(int n) {
   }
   std::lock_guard<std::mutex> lk(g_variant_mu);
   auto it = g_variant.find(n);
-  return it == g_variant.end() ? 0 : it->second;
+  return it == g_variant.end() ? kDefaultUpdateVariant : it->second;
 }
 void set_update_variant(int n, int v) {
   std::lock_guard<std::mutex> lk(g_variant_mu);

@@ -46,6 +46,10 @@ bool use_group_seq(int groups);
 
 // Process-wide choice of update-kernel variant per tile size (autotuned on
 // first use; FPM_UPDATE_VARIANT=k forces one).
+// The variant used where nothing has been tuned (the server): the four-round
+// 8-lane form, the fastest measured at n = 128 (n = 256 runs its 16-lane
+// kernel for every variant but 1).
+constexpr int kDefaultUpdateVariant = 7;
 int update_variant(int n);
 void set_update_variant(int n, int v);
 bool update_variant_known(int n);

@@ -11,6 +11,7 @@
 // what it is batched with (one workgroup per update, per-tile reductions in
 // fixed order), so a result is bitwise the same alone and in a mix.
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -82,6 +83,7 @@ struct fpm_server_s {
   int max_slots = 0;
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t stream2 = nullptr;  // second half of each tick's batch
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -93,7 +95,14 @@ struct fpm_server_s {
   std::thread worker;
   // device tables rebuilt per tick
   DevBuf table, items, steps, ids, jobs;
-  DevBuf big_scratch;  // transpose slots of the n = 256 kernel, allocated on first use
+  DevBuf items2, steps2, ids2;  // work lists of the second half
+  // host copies of the halves' work lists: they stay alive until the tick's
+  // synchronisation, so the asynchronous uploads never read freed memory
+  std::vector<Item> host_items[2];
+  std::vector<StepTile> host_steps[2];
+  std::vector<int> host_ids[2];
+  // transpose slots of the n = 256 kernel, one set per half, allocated on first use
+  DevBuf big_scratch;
   std::vector<int> free_slots;
   std::vector<TileDev> host_table;
   fpm_status fatal = FPM_OK;
@@ -102,6 +111,7 @@ struct fpm_server_s {
   bool admit(Request* r, std::string& err);
   void release(Request* r);
   hipError_t tick(std::vector<Request*>& batch);
+  hipError_t tick_part(std::vector<Request*>& batch, int part);
   hipError_t finish(Request* r);
 };
 
@@ -251,11 +261,51 @@ hipError_t fpm_server_s::finish(Request* r) {
   return e;
 }
 
-// One scheduler tick: one whole iteration of every admitted request -- its
-// dependent LED-group steps enqueued in stream order (step s of every
-// request in one launch per (size, precision) class, then the group means
-// of step s), then the iteration ends -- and one host synchronisation.
+// One scheduler tick: one whole iteration of every admitted request, and one
+// host synchronisation.  The batch is split in two halves, balanced by update
+// work, each on its own stream, so that one half's partial last waves and
+// short launches overlap the other half's updates; a request's own launches
+// keep their order, so its result does not depend on the split.
 hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
+  std::vector<Request*> half[2];
+  {
+    std::vector<Request*> ord = batch;
+    auto cost = [](const Request* r) { return (double)r->plan.L * r->plan.n * r->plan.n; };
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](const Request* a, const Request* b) { return cost(a) > cost(b); });
+    double load[2] = {0.0, 0.0};
+    // split only while a step's launches leave the GPU short of work (fewer
+    // than two workgroups per CU on average): then the halves overlap; with
+    // more work per step, twice the launches only add their fixed costs
+    double items = 0.0;
+    int steps_max = 1;
+    for (const Request* r : batch) {
+      items += r->plan.L;
+      steps_max = std::max(steps_max, r->plan.nsteps);
+    }
+    const char* one = std::getenv("FPM_SERVER_ONE_STREAM");  // 1: never split (comparisons)
+    const bool split = !(one && one[0] == '1') && items / steps_max < 160.0;
+    for (Request* r : ord) {
+      const int p = split && load[1] < load[0] ? 1 : 0;
+      half[p].push_back(r);
+      load[p] += cost(r);
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < 2 && e == hipSuccess; ++p)
+    if (!half[p].empty()) e = tick_part(half[p], p);
+  const hipError_t e0 = hipStreamSynchronize(stream), e1 = hipStreamSynchronize(stream2);
+  return e != hipSuccess ? e : (e0 != hipSuccess ? e0 : e1);
+}
+
+// One half of a tick on its own stream: the dependent LED-group steps in
+// stream order (step s of every request in one launch per (size, precision)
+// class, then the group means of step s), then the iteration ends.
+hipError_t fpm_server_s::tick_part(std::vector<Request*>& batch, int part) {
+  const hipStream_t stream = part ? stream2 : this->stream;
+  DevBuf& items = part ? items2 : this->items;
+  DevBuf& steps = part ? steps2 : this->steps;
+  DevBuf& ids = part ? ids2 : this->ids;
   struct ClassLaunch {
     std::pair<int, int> cls;  // (n, precision)
     size_t off, count;
@@ -266,8 +316,10 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
     max_steps = std::max(max_steps, r->plan.nsteps);
     n_max = std::max(n_max, r->plan.n);
   }
-  std::vector<Item> flat;
-  std::vector<StepTile> st;
+  std::vector<Item>& flat = host_items[part];
+  std::vector<StepTile>& st = host_steps[part];
+  flat.clear();
+  st.clear();
   std::vector<std::vector<ClassLaunch>> step_launches(max_steps);
   std::vector<std::pair<size_t, size_t>> step_means(max_steps);  // StepTile range per step
   for (int s = 0; s < max_steps; ++s) {
@@ -321,14 +373,14 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
       // one update variant per size for the whole process: if no plan has
       // tuned this size yet, the server fixes the default, so served and
       // planned results stay bitwise equal
-      if (!update_variant_known(l.n)) set_update_variant(l.n, 0);
+      if (!update_variant_known(l.n)) set_update_variant(l.n, kDefaultUpdateVariant);
       l.nd_max = cl.nd_max;
       l.box_max = cl.box_max;
       l.count = (int)cl.count;
       if (l.prec != FPM_PREC_FP32_FFT) e = dft_tables(l.n, l.prec, &l.tabE, &l.tabF);
       if (e == hipSuccess && l.n == 256) {
-        e = big_scratch.alloc(big_scratch_bytes(256));
-        l.big_scratch = (float2*)big_scratch.p;
+        e = big_scratch.alloc(2 * big_scratch_bytes(256));
+        l.big_scratch = (float2*)((char*)big_scratch.p + (size_t)part * big_scratch_bytes(256));
       }
       if (e == hipSuccess) e = launch_update_class(l, tab, (const Item*)items.p + cl.off, stream);
     }
@@ -341,7 +393,8 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
   if (e == hipSuccess) {
     std::map<int, std::vector<int>> by_iter;
     for (Request* r : batch) by_iter[r->iter].push_back(r->slot);
-    std::vector<int> flat_ids;
+    std::vector<int>& flat_ids = host_ids[part];
+    flat_ids.clear();
     for (auto& kv : by_iter) flat_ids.insert(flat_ids.end(), kv.second.begin(), kv.second.end());
     e = hipMemcpyAsync(ids.p, flat_ids.data(), flat_ids.size() * sizeof(int),
                        hipMemcpyHostToDevice, stream);
@@ -357,7 +410,6 @@ hipError_t fpm_server_s::tick(std::vector<Request*>& batch) {
       off += kv.second.size();
     }
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   return e;
 }
 void fpm_server_s::run() {
@@ -460,8 +512,11 @@ fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_ser
   fpm_status st = FPM_OK;
   if (!hip_ok(hipGetDevice(&s->device), "hipGetDevice", &st) ||
       !hip_ok(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate", &st) ||
+      !hip_ok(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking), "hipStreamCreate",
+              &st) ||
       !hip_ok(s->table.alloc(sizeof(TileDev) * max_slots), "hipMalloc(table)", &st) ||
-      !hip_ok(s->ids.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st))
+      !hip_ok(s->ids.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st) ||
+      !hip_ok(s->ids2.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st))
     return st;
   s->host_table.assign(max_slots, TileDev{});
   for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
@@ -480,8 +535,10 @@ void fpm_server_destroy(fpm_server_t* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->stream2);
   for (auto& kv : s->all) s->release(kv.second.get());
   (void)hipStreamDestroy(s->stream);
+  (void)hipStreamDestroy(s->stream2);
   delete s;
 }
 
