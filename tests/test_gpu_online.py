@@ -33,14 +33,13 @@ def fpm():
     return fpm
 
 
-def make_tiles(orc, pupil, precs=(0, 0, 0, 1)):
-    """Tiles of 64, 96 and 128 px on one 11 x 11 board (same L and NA order),
-    own positions and defocus."""
+def make_tiles(orc, pupil, precs=(0, 0, 0, 1), sizes=(64, 96, 128, 64)):
+    """Tiles of 64-256 px on one 11 x 11 board (same L and NA order), own
+    positions and defocus."""
     rng = np.random.default_rng(2203 + pupil)
-    sizes = [64, 96, 128, 64]
     descs, Is = [], []
     for n, prec in zip(sizes, precs):
-        d = fpm_synth.TileDesc(n=n, upsample=3 if n == 128 else 4, led_rows=11, led_cols=11,
+        d = fpm_synth.TileDesc(n=n, upsample=3 if n >= 128 else 4, led_rows=11, led_cols=11,
                                iterations=3, schedule=fpm_synth.SCHED_SEQUENTIAL,
                                pupil_update=pupil, precision=prec,
                                tile_x_um=float(rng.uniform(-1000, 1000)),
@@ -95,7 +94,8 @@ def same(a, b):
 
 @pytest.mark.parametrize("pupil", [0, 1])
 def test_online_in_na_order_equals_offline_bitwise(fpm, orc, pupil):
-    descs, Is = make_tiles(orc, pupil)
+    """Five tiles, one of them 256 px (the persistent kernel), one MFMA."""
+    descs, Is = make_tiles(orc, pupil, precs=(0, 0, 0, 1, 0), sizes=(64, 96, 128, 64, 256))
     _, ref = offline(fpm, descs, Is)
     plan = fpm.Plan(descs)
     order = plan.tables(0)[1]
