@@ -47,7 +47,7 @@ typedef enum {
   FPM_E_DEVICE = -4,      /* a HIP call failed                                */
   FPM_E_DIVERGED = -5,    /* a residual became non-finite                     */
   FPM_E_CANCELLED = -6,   /* the request was cancelled                        */
-  FPM_E_UNSUPPORTED = -7, /* tile size or precision this build does not run   */
+  FPM_E_UNSUPPORTED = -7, /* tile size or precision the library does not run */
   FPM_E_STATE = -8        /* call out of order (online session open/closed)   */
 } fpm_status;
 
