@@ -577,6 +577,21 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
   }
 }
 
+// XCD-aware order of a launch's items: the GPU hands workgroup b to XCD
+// b mod kXcds, so the items (grouped by tile) are dealt out in kXcds
+// contiguous blocks, one per XCD, and a tile's LED-group members run on one
+// XCD and read its pupil from that XCD's L2.  The grid is kXcds * per
+// workgroups; -1: no item (the last block is short).
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int xcd_grid(int count) {
+  return (count + kXcds - 1) / kXcds * kXcds;
+}
+__device__ __forceinline__ int xcd_item(int b, int count) {
+  const int per = (count + kXcds - 1) / kXcds;
+  const int ii = (b % kXcds) * per + b / kXcds;
+  return ii < count ? ii : -1;
+}
+
 }  // namespace
 
 // ===================================================== the update kernel
@@ -590,7 +605,8 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
 template <int n, int PAD, int Q, bool SEQ>
 __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict__ tiles,
                                                        const Item* __restrict__ items,
-                                                       const int2* __restrict__ ranges) {
+                                                       const int2* __restrict__ ranges,
+                                                       int count) {
   constexpr int R = n / Q;
   constexpr int NT = n * Q;
   constexpr int NW = NT / 64;
@@ -712,7 +728,8 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
       lds_barrier();  // LDS and reductions are reused by the next member
     }
   } else {
-    run_item((int)blockIdx.x);
+    const int ii = xcd_item((int)blockIdx.x, count);
+    if (ii >= 0) run_item(ii);
   }
 }
 
@@ -727,7 +744,7 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
 template <int n, int PAD, int Q, int ROUNDS, bool SEQ>
 __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void update_kernel_rounds(
     const TileDev* __restrict__ tiles, const Item* __restrict__ items,
-    const int2* __restrict__ ranges) {
+    const int2* __restrict__ ranges, int count) {
   constexpr int R = n / Q;
   constexpr int NT = n * Q / ROUNDS;
   constexpr int LPR = NT / Q;  // lines per round
@@ -851,7 +868,8 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
       lds_barrier();  // LDS and reductions are reused by the next member
     }
   } else {
-    run_item((int)blockIdx.x);
+    const int ii = xcd_item((int)blockIdx.x, count);
+    if (ii >= 0) run_item(ii);
   }
 }
 
@@ -1397,10 +1415,10 @@ hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, 
   const size_t lds = update_lds<n, PAD>(nd_max);
   if (ranges) {
     hipLaunchKernelGGL((update_kernel<n, PAD, Q, true>), dim3(nranges), dim3(n * Q), lds, st,
-                       tiles, items, ranges);
+                       tiles, items, ranges, nranges);
   } else {
-    hipLaunchKernelGGL((update_kernel<n, PAD, Q, false>), dim3(count), dim3(n * Q), lds, st,
-                       tiles, items, nullptr);
+    hipLaunchKernelGGL((update_kernel<n, PAD, Q, false>), dim3(xcd_grid(count)), dim3(n * Q), lds,
+                       st, tiles, items, nullptr, count);
   }
   return hipGetLastError();
 }
@@ -1411,10 +1429,10 @@ hipError_t launch_update_rounds(const TileDev* tiles, const Item* items, int cou
   const size_t lds = update_lds<n, PAD>(nd_max > n / 2 ? nd_max : n / 2);
   if (ranges) {
     hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, true>), dim3(nranges),
-                       dim3(n * Q / ROUNDS), lds, st, tiles, items, ranges);
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, ranges, nranges);
   } else {
-    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, false>), dim3(count),
-                       dim3(n * Q / ROUNDS), lds, st, tiles, items, nullptr);
+    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, false>), dim3(xcd_grid(count)),
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, nullptr, count);
   }
   return hipGetLastError();
 }
