@@ -22,6 +22,7 @@
 #include <cstdint>
 
 #include "fpm_internal.h"
+#include "xcd_order.h"
 
 namespace fpm {
 
@@ -577,21 +578,6 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
   }
 }
 
-// XCD-aware order of a launch's items: the GPU hands workgroup b to XCD
-// b mod kXcds, so the items (grouped by tile) are dealt out in kXcds
-// contiguous blocks, one per XCD, and a tile's LED-group members run on one
-// XCD and read its pupil from that XCD's L2.  The grid is kXcds * per
-// workgroups; -1: no item (the last block is short).
-constexpr int kXcds = 8;
-__host__ __device__ constexpr int xcd_grid(int count) {
-  return (count + kXcds - 1) / kXcds * kXcds;
-}
-__device__ __forceinline__ int xcd_item(int b, int count) {
-  const int per = (count + kXcds - 1) / kXcds;
-  const int ii = (b % kXcds) * per + b / kXcds;
-  return ii < count ? ii : -1;
-}
-
 }  // namespace
 
 // ===================================================== the update kernel
@@ -945,7 +931,13 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
   float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
   __syncthreads();
 
-  for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+  // items in XCD-aware order: the workgroups on XCD x (b mod kXcds = x; the
+  // grid is a multiple of kXcds) run block x of the items, so a tile's
+  // members share its pupil in that XCD's L2
+  const int per = (count + kXcds - 1) / kXcds, wg_per_xcd = (int)gridDim.x / kXcds;
+  const int xcd = (int)blockIdx.x % kXcds;
+  for (int m = (int)blockIdx.x / kXcds; m < per && xcd * per + m < count; m += wg_per_xcd) {
+    const int ii = xcd * per + m;
     // lane indices are re-derived per item through an opaque copy, so the
     // compiler does not hoist every address they feed out of the item loop
     // (that kept hundreds of values live across the whole kernel)
@@ -1518,7 +1510,8 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
   if (n == 256) {
     if (!big_scratch) return hipErrorInvalidValue;
     // 16 lanes per line (R = 16: no spills); variant 1: 8 lanes (R = 32)
-    const int grid = count < kBigSlots ? count : kBigSlots;
+    const int grid = xcd_grid(count) < kBigSlots ? xcd_grid(count) : kBigSlots;
+    static_assert(kBigSlots % kXcds == 0, "whole XCD blocks of slots");
     if (variant == 1)
       hipLaunchKernelGGL((update_kernel_big<256, 8>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);

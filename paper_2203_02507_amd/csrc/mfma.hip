@@ -35,6 +35,7 @@
 #include <tuple>
 
 #include "fpm_internal.h"
+#include "xcd_order.h"
 
 namespace fpm {
 
@@ -215,7 +216,8 @@ template <int n, int MS, int PREC>
 __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __restrict__ tiles,
                                                             const Item* __restrict__ items,
                                                             const uint16_t* __restrict__ tabE,
-                                                            const uint16_t* __restrict__ tabF) {
+                                                            const uint16_t* __restrict__ tabF,
+                                                            int count) {
   using G = Geo<n>;
   constexpr int W = G::W, NT = G::NT, MT = G::MT, KS = G::KS;
   constexpr int T4W = (MS * MS + W - 1) / W;  // stage-4 output tiles per wave
@@ -223,7 +225,9 @@ __global__ __launch_bounds__(2 * n) void mfma_update_kernel(const TileDev* __res
   __shared__ float red_p[W], red_f[W], red_v[W];
   __shared__ double red_e[W], red_i[W];
 
-  const Item it = items[blockIdx.x];
+  const int ii = xcd_item((int)blockIdx.x, count);
+  if (ii < 0) return;  // the whole workgroup: past the last item
+  const Item it = items[ii];
   const TileDev t = tiles[it.tile];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, h = lane >> 5, c32 = lane & 31;
@@ -673,8 +677,8 @@ hipError_t launch_mfma_nsp(const TileDev* tiles, const Item* items, int count, i
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
   }
   const size_t lds = mfma_lds_bytes<n>(box_max);
-  hipLaunchKernelGGL((mfma_update_kernel<n, MS, PREC>), dim3(count), dim3(Geo<n>::NT), lds, st,
-                     tiles, items, E, F);
+  hipLaunchKernelGGL((mfma_update_kernel<n, MS, PREC>), dim3(xcd_grid(count)), dim3(Geo<n>::NT),
+                     lds, st, tiles, items, E, F, count);
   return hipGetLastError();
 }
 
