@@ -308,9 +308,10 @@ def online_bench(fpm, tds, I, tiles_per_side: int, counts=(16, 256)):
 
 def host_mode_bench(fpm, plan, I, updates):
     """fpm_reconstruct with host buffers: the intensity stack (pageable numpy)
-    validated on the host, copied to the device, the reconstruction, and the
-    object, pupil and residuals copied back -- the rate a caller holding its
-    data in host memory sees (PCIe included).  One run after a warm-up."""
+    validated by host threads into pinned chunks whose uploads overlap the
+    checking, the reconstruction, and the object, pupil and residuals copied
+    back -- the rate a caller holding its data in host memory sees (PCIe
+    included).  One run after a warm-up."""
     import numpy as np
     Ih = I.cpu().numpy()
     obj = np.empty(plan.total_object * 2, np.float32)
@@ -322,8 +323,8 @@ def host_mode_bench(fpm, plan, I, updates):
     s = time.perf_counter() - t0
     return {"ms": round(s * 1e3, 1), "updates_per_s": round(updates / s, 1),
             "intensity_gib": round(Ih.nbytes / 2**30, 2),
-            "note": "host validation + pageable H2D of the stack + reconstruction + D2H of "
-                    "object, pupil and residuals; not the benchmark value"}
+            "note": "threaded host validation into pinned chunks + overlapped H2D of the stack + "
+                    "reconstruction + D2H of object, pupil and residuals; not the benchmark value"}
 
 
 def paper_workload_bench(fpm, reps: int = 3):

@@ -1,11 +1,13 @@
 // C ABI entry points for plans (include/fpm.h).  No exception crosses the
 // boundary; every failure becomes an fpm_status plus a thread-local message.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fpm_internal.h"
@@ -106,6 +108,65 @@ fpm_status collect_outputs(fpm_plan_t* plan, fpm_mem where, void* object_out, vo
       if (!std::isfinite(res_host[i]))
         return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
     if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
+  }
+  return FPM_OK;
+}
+
+// Host intensities -> ex.I_stage, validated on the way: chunks are checked
+// and copied into one of two pinned buffers by host threads, and each chunk's
+// upload overlaps the checking of the next.  FPM_E_ARG names the first bad
+// value; nothing is launched on the stack then.
+fpm_status stage_host_intensities(Executor& ex, const float* src, hipStream_t s) {
+  constexpr int64_t kChunk = (int64_t)32 << 20;  // floats per chunk (128 MiB)
+  fpm_status st = FPM_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (!ex.host_pin[k] &&
+        !hip_ok(hipHostMalloc(&ex.host_pin[k], sizeof(float) * kChunk, hipHostMallocDefault),
+                "hipHostMalloc(intensity staging)", &st))
+      return st;
+    if (!ex.host_pin_ev[k] &&
+        !hip_ok(hipEventCreateWithFlags(&ex.host_pin_ev[k], hipEventDisableTiming),
+                "hipEventCreate", &st))
+      return st;
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nthreads = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+  bool armed[2] = {false, false};
+  for (int64_t c0 = 0, c = 0; c0 < ex.total_I; c0 += kChunk, ++c) {
+    const int k = (int)(c & 1);
+    const int64_t len = std::min(kChunk, ex.total_I - c0);
+    if (armed[k] && !hip_ok(hipEventSynchronize(ex.host_pin_ev[k]), "hipEventSynchronize", &st))
+      return st;
+    float* dst = (float*)ex.host_pin[k];
+    std::vector<int64_t> bad(nthreads, -1);
+    std::vector<std::thread> pool;
+    const int64_t part = (len + nthreads - 1) / nthreads;
+    for (int w = 0; w < nthreads; ++w)
+      pool.emplace_back([&, w] {
+        const int64_t b = w * part, e = std::min(len, b + part);
+        for (int64_t i = b; i < e; ++i) {
+          const float v = src[c0 + i];
+          if (!(v >= 0.0f) || !std::isfinite(v)) {
+            bad[w] = c0 + i;
+            return;
+          }
+          dst[i] = v;
+        }
+      });
+    for (auto& th : pool) th.join();
+    for (int64_t b : bad)
+      if (b >= 0) {
+        // let the copies already queued finish before the caller reuses anything
+        (void)hipStreamSynchronize(s);
+        return fail(FPM_E_ARG, "fpm_reconstruct: intensity " + std::to_string(b) +
+                                   " is negative or not finite");
+      }
+    if (!hip_ok(hipMemcpyAsync((float*)ex.I_stage.p + c0, dst, sizeof(float) * len,
+                               hipMemcpyHostToDevice, s),
+                "H2D intensity", &st) ||
+        !hip_ok(hipEventRecord(ex.host_pin_ev[k], s), "hipEventRecord", &st))
+      return st;
+    armed[k] = true;
   }
   return FPM_OK;
 }
@@ -301,16 +362,8 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   const size_t int_bytes = sizeof(float) * ex.total_I;
   const float* I = intensity;
   if (where == FPM_MEM_HOST) {
-    for (int64_t i = 0; i < ex.total_I; ++i) {
-      const float v = intensity[i];
-      if (!(v >= 0.0f) || !std::isfinite(v))
-        return fail(FPM_E_ARG, "fpm_reconstruct: intensity " + std::to_string(i) +
-                                   " is negative or not finite");
-    }
-    if (!hip_ok(ex.I_stage.alloc(int_bytes), "hipMalloc(intensity stage)", &st) ||
-        !hip_ok(hipMemcpyAsync(ex.I_stage.p, intensity, int_bytes, hipMemcpyHostToDevice, s),
-                "H2D intensity", &st))
-      return st;
+    if (!hip_ok(ex.I_stage.alloc(int_bytes), "hipMalloc(intensity stage)", &st)) return st;
+    if ((st = stage_host_intensities(ex, intensity, s)) != FPM_OK) return st;
     I = (const float*)ex.I_stage.p;
   }
   if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, I,

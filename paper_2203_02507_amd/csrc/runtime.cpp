@@ -97,6 +97,10 @@ Executor::~Executor() {
   if (fork_ev) hipEventDestroy(fork_ev);
   if (online_ev) hipEventDestroy(online_ev);
   if (online_pin) hipHostFree(online_pin);
+  for (int k = 0; k < 2; ++k) {
+    if (host_pin_ev[k]) hipEventDestroy(host_pin_ev[k]);
+    if (host_pin[k]) hipHostFree(host_pin[k]);
+  }
 }
 
 namespace {

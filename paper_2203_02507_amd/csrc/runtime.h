@@ -106,6 +106,9 @@ struct Executor {
   int64_t online_push_floats = 0;     // floats of one push: sum over tiles of n^2
   std::vector<char> online_pushed;
   int online_count = -1;  // -1: no online session
+  // host-buffer reconstructions: two pinned staging chunks and their copy events
+  void* host_pin[2] = {nullptr, nullptr};
+  hipEvent_t host_pin_ev[2] = {nullptr, nullptr};
   // host pushes: pinned staging, reused once the previous copy has left it
   void* online_pin = nullptr;
   hipEvent_t online_ev = nullptr;
