@@ -190,7 +190,11 @@ fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
  * `hip_stream`, returns without waiting (intensities are not validated).
  * FPM_MEM_HOST: the intensities are validated (FPM_E_ARG on NaN, Inf or a
  * negative value), copied, and the call synchronises; FPM_E_DIVERGED if a
- * residual is not finite. */
+ * residual is not finite.
+ * The plan's tiles run as independent chains on streams of the library's
+ * own, forked from `hip_stream` and joined back into it with events, so the
+ * work is ordered on `hip_stream` as one operation (and can be captured into
+ * a caller's graph); FPM_CHAINS=1..4 sets the number of chains. */
 fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem where,
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
