@@ -193,8 +193,8 @@ fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
  * residual is not finite.
  * The plan's tiles run as independent chains on streams of the library's
  * own, forked from `hip_stream` and joined back into it with events, so the
- * work is ordered on `hip_stream` as one operation (and can be captured into
- * a caller's graph); FPM_CHAINS=1..4 sets the number of chains. */
+ * work is ordered on `hip_stream` as one operation; FPM_CHAINS=1..4 sets the
+ * number of chains. */
 fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem where,
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
