@@ -769,7 +769,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
-      const int q = opaque(q_item);
+      const int q = q_item;
       const int kx = t.kx0 + line;
       pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
       line_dit<n, true, Q, PT>(a, q, tw);
@@ -786,11 +786,9 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
 #pragma unroll 1
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
-    const int q = opaque(q_item);
-    load_rows<n, PAD, Q>(sbuf, t.kx0, t.nd, line, q, a);
-    line_dit<n, true, Q, PT>(a, q, tw);
-    // the intensities are loaded after the transform (registers); the other
-    // workgroup on the CU covers the wait
+    const int q = q_item;
+    // the row's intensities are requested first, so that their latency
+    // overlaps the row transform
     float iv[R];
 #pragma unroll
     for (int v = 0; v < R / 4; ++v) {
@@ -800,6 +798,8 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
       iv[4 * v + 2] = f.z;
       iv[4 * v + 3] = f.w;
     }
+    load_rows<n, PAD, Q>(sbuf, t.kx0, t.nd, line, q, a);
+    line_dit<n, true, Q, PT>(a, q, tw);
     float e_acc = 0.0f, i_acc = 0.0f;
     modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
     {
@@ -827,7 +827,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
-      const int q = opaque(q_item);
+      const int q = q_item;
       const float2* srcp = sbuf + line * PT + xc;
 #pragma unroll
       for (int m = 0; m < R; ++m) a[m] = srcp[m];
