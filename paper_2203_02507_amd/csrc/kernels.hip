@@ -529,13 +529,29 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 // order): the increments are summed in place in slot 0, and the last member
 // applies P <- P + sum / count -- the same operations in the same order as
 // pupil_reduce_kernel, so both forms give the same bits.
-template <int n, int Q = kQ, bool SEQ = false>
+// The stored spectrum of a support column (the values update_column reads),
+// loaded ahead of the column transform where registers allow.
+template <int n, int Q = kQ>
+__device__ __forceinline__ void load_column(__amdgpu_buffer_rsrc_t Sw, int N, int kx, int2 ch,
+                                            int q, float2 (&xs)[n / Q]) {
+  constexpr int R = n / Q;
+  const int s0 = (q * N + kx) * 8;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ky = q + Q * k;
+    const bool in = ky >= ch.x && ky <= ch.y;
+    xs[k] = bload2(Sw, in ? s0 + k * (Q * 8) * N : kOob);
+  }
+}
+
+template <int n, int Q = kQ, bool SEQ = false, bool PRE = false>
 __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Sw,
                                               __amdgpu_buffer_rsrc_t Pw,
                                               __amdgpu_buffer_rsrc_t Dw, int N, int kx, int2 ch,
                                               int q, float sigf, float pmax2, float smax,
-                                              int mode, int slot = 0, int count = 1) {
+                                              int mode, int slot = 0, int count = 1,
+                                              const float2* xs_pre = nullptr) {
   constexpr int R = n / Q;
   const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
   const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
@@ -547,7 +563,8 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
     const bool in = ky >= ch.x && ky <= ch.y;
     const int offS = in ? s0 + k * (Q * 8) * N : kOob;
     const int offP = in ? p0 + k * (Q * 8 * n) : kOob;
-    const float2 xs = bload2(Sw, offS);  // stored spectrum (this WG's own support pixels)
+    // stored spectrum (this WG's own support pixels), loaded here or ahead
+    const float2 xs = PRE ? xs_pre[k] : bload2(Sw, offS);
     const float2 pv = bload2(Pw, offP);
     // explicit fused multiply-adds: every instantiation of this function
     // rounds the update identically, whatever the compiler contracts elsewhere
@@ -828,13 +845,17 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
       const int q = q_item;
+      const int kx = t.kx0 + line;
+      const int2 ch = t.chord[kx];
+      // the column's stored spectrum is requested before its transform
+      float2 xs[R];
+      load_column<n, Q>(Sw, N, kx, ch, q, xs);
       const float2* srcp = sbuf + line * PT + xc;
 #pragma unroll
       for (int m = 0; m < R; ++m) a[m] = srcp[m];
       line_dif<n, false, Q, PT>(a, q, tw);
-      const int kx = t.kx0 + line;
-      update_column<n, Q, SEQ>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, mode,
-                               it.slot, it.gsize);
+      update_column<n, Q, SEQ, true>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
+                                     it.slot, it.gsize, xs);
     }
   }
   if (tid == 0) {
