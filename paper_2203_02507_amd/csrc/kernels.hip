@@ -543,6 +543,18 @@ __device__ __forceinline__ void load_column(__amdgpu_buffer_rsrc_t Sw, int N, in
     xs[k] = bload2(Sw, in ? s0 + k * (Q * 8) * N : kOob);
   }
 }
+template <int n, int Q = kQ>
+__device__ __forceinline__ void load_pupil_column(__amdgpu_buffer_rsrc_t Pw, int kx, int2 ch,
+                                                  int q, float2 (&pv)[n / Q]) {
+  constexpr int R = n / Q;
+  const int p0 = (q * n + kx) * 8;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ky = q + Q * k;
+    const bool in = ky >= ch.x && ky <= ch.y;
+    pv[k] = bload2(Pw, in ? p0 + k * (Q * 8 * n) : kOob);
+  }
+}
 
 template <int n, int Q = kQ, bool SEQ = false, bool PRE = false>
 __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
@@ -551,7 +563,8 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Dw, int N, int kx, int2 ch,
                                               int q, float sigf, float pmax2, float smax,
                                               int mode, int slot = 0, int count = 1,
-                                              const float2* xs_pre = nullptr) {
+                                              const float2* xs_pre = nullptr,
+                                              const float2* pv_pre = nullptr) {
   constexpr int R = n / Q;
   const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
   const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
@@ -565,7 +578,7 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
     const int offP = in ? p0 + k * (Q * 8 * n) : kOob;
     // stored spectrum (this WG's own support pixels), loaded here or ahead
     const float2 xs = PRE ? xs_pre[k] : bload2(Sw, offS);
-    const float2 pv = bload2(Pw, offP);
+    const float2 pv = PRE ? pv_pre[k] : bload2(Pw, offP);
     // explicit fused multiply-adds: every instantiation of this function
     // rounds the update identically, whatever the compiler contracts elsewhere
     const float2 px = cmul_fma(pv, xs);  // D = Phi' - sigma P X
@@ -848,14 +861,15 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
       const int kx = t.kx0 + line;
       const int2 ch = t.chord[kx];
       // the column's stored spectrum is requested before its transform
-      float2 xs[R];
+      float2 xs[R], pv[R];
       load_column<n, Q>(Sw, N, kx, ch, q, xs);
+      load_pupil_column<n, Q>(Pw, kx, ch, q, pv);
       const float2* srcp = sbuf + line * PT + xc;
 #pragma unroll
       for (int m = 0; m < R; ++m) a[m] = srcp[m];
       line_dif<n, false, Q, PT>(a, q, tw);
       update_column<n, Q, SEQ, true>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
-                                     it.slot, it.gsize, xs);
+                                     it.slot, it.gsize, xs, pv);
     }
   }
   if (tid == 0) {
