@@ -1,9 +1,11 @@
 // C ABI entry points for plans (include/fpm.h).  No exception crosses the
 // boundary; every failure becomes an fpm_status plus a thread-local message.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <mutex>
 #include <new>
 #include <string>
@@ -129,8 +131,9 @@ fpm_status stage_host_intensities(Executor& ex, const float* src, hipStream_t s)
                 "hipEventCreate", &st))
       return st;
   }
+  constexpr int kMaxThreads = 16;
   const unsigned hw = std::thread::hardware_concurrency();
-  const int nthreads = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+  const int nthreads = (int)std::max(1u, std::min((unsigned)kMaxThreads, hw ? hw : 1u));
   bool armed[2] = {false, false};
   for (int64_t c0 = 0, c = 0; c0 < ex.total_I; c0 += kChunk, ++c) {
     const int k = (int)(c & 1);
@@ -138,21 +141,34 @@ fpm_status stage_host_intensities(Executor& ex, const float* src, hipStream_t s)
     if (armed[k] && !hip_ok(hipEventSynchronize(ex.host_pin_ev[k]), "hipEventSynchronize", &st))
       return st;
     float* dst = (float*)ex.host_pin[k];
-    std::vector<int64_t> bad(nthreads, -1);
-    std::vector<std::thread> pool;
+    std::array<int64_t, kMaxThreads> bad;
+    bad.fill(-1);
     const int64_t part = (len + nthreads - 1) / nthreads;
-    for (int w = 0; w < nthreads; ++w)
-      pool.emplace_back([&, w] {
-        const int64_t b = w * part, e = std::min(len, b + part);
-        for (int64_t i = b; i < e; ++i) {
-          const float v = src[c0 + i];
-          if (!(v >= 0.0f) || !std::isfinite(v)) {
-            bad[w] = c0 + i;
-            return;
-          }
-          dst[i] = v;
+    auto check = [&](int w) {
+      const int64_t b = w * part, e = std::min(len, b + part);
+      for (int64_t i = b; i < e; ++i) {
+        const float v = src[c0 + i];
+        if (!(v >= 0.0f) || !std::isfinite(v)) {
+          bad[w] = c0 + i;
+          return;
         }
-      });
+        dst[i] = v;
+      }
+    };
+    // parts 1.. on helper threads, part 0 here; a part whose thread cannot be
+    // started also runs here, so no exception leaves the C ABI
+    std::vector<std::thread> pool;
+    int started = 0;
+    try {
+      pool.reserve(nthreads - 1);
+      for (int w = 1; w < nthreads; ++w) {
+        pool.emplace_back(check, w);
+        ++started;
+      }
+    } catch (const std::exception&) {
+    }
+    check(0);
+    for (int w = started + 1; w < nthreads; ++w) check(w);
     for (auto& th : pool) th.join();
     for (int64_t b : bad)
       if (b >= 0) {

@@ -17,6 +17,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -510,6 +511,12 @@ fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_ser
   s->max_slots = max_slots;
   s->t0 = std::chrono::steady_clock::now();
   fpm_status st = FPM_OK;
+  // on failure: the streams made so far are destroyed (device buffers free themselves)
+  auto undo = [&](fpm_status code) {
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->stream2) (void)hipStreamDestroy(s->stream2);
+    return code;
+  };
   if (!hip_ok(hipGetDevice(&s->device), "hipGetDevice", &st) ||
       !hip_ok(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate", &st) ||
       !hip_ok(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking), "hipStreamCreate",
@@ -517,12 +524,17 @@ fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_ser
       !hip_ok(s->table.alloc(sizeof(TileDev) * max_slots), "hipMalloc(table)", &st) ||
       !hip_ok(s->ids.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st) ||
       !hip_ok(s->ids2.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st))
-    return st;
-  s->host_table.assign(max_slots, TileDev{});
-  for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
-  fpm_server_s* raw = s.release();
-  raw->worker = std::thread([raw] { raw->run(); });
-  *out = raw;
+    return undo(st);
+  try {
+    s->host_table.assign(max_slots, TileDev{});
+    s->free_slots.reserve(max_slots);
+    for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    fpm_server_s* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+  } catch (const std::exception&) {
+    return undo(fail(FPM_E_NOMEM, "fpm_server_create: host allocation or worker start failed"));
+  }
+  *out = s.release();
   return FPM_OK;
 }
 
