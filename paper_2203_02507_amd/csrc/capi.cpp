@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -198,21 +199,18 @@ const char* fpm_last_error(void) { return g_last_error.c_str(); }
 
 const char* fpm_version(void) { return "fpm-mi355x 0.1 (gfx950)"; }
 
-fpm_status fpm_plan(const fpm_tile_desc* tiles, int32_t ntiles, fpm_plan_t** out) {
+fpm_status fpm_plan(const fpm_tile_desc* tiles, int32_t ntiles, fpm_plan_t** out) try {
   if (!tiles || !out || ntiles < 1 || ntiles > (1 << 20))
     return fail(FPM_E_ARG, "fpm_plan: NULL argument or ntiles out of range");
   *out = nullptr;
-  fpm_plan_t* p = new (std::nothrow) fpm_plan_t();
+  std::unique_ptr<fpm_plan_t> p(new (std::nothrow) fpm_plan_t());
   if (!p) return fail(FPM_E_NOMEM, "fpm_plan: host allocation failed");
   p->tiles.resize(ntiles);
   int64_t io = 0, oo = 0, po = 0, ro = 0;
   for (int t = 0; t < ntiles; ++t) {
     std::string err;
     const fpm_status s = build_tile_plan(tiles[t], p->tiles[t], err);
-    if (s != FPM_OK) {
-      delete p;
-      return fail(s, "tile " + std::to_string(t) + ": " + err);
-    }
+    if (s != FPM_OK) return fail(s, "tile " + std::to_string(t) + ": " + err);
     TilePlan& tp = p->tiles[t];
     tp.i_off = io;
     tp.o_off = oo;
@@ -223,9 +221,10 @@ fpm_status fpm_plan(const fpm_tile_desc* tiles, int32_t ntiles, fpm_plan_t** out
     po += (int64_t)tp.n * tp.n;
     ro += tp.d.iterations;
   }
-  *out = p;
+  *out = p.release();
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_plan")
 
 void fpm_plan_destroy(fpm_plan_t* plan) {
   if (!plan) return;
@@ -238,7 +237,7 @@ void fpm_plan_destroy(fpm_plan_t* plan) {
   delete plan;
 }
 
-fpm_status fpm_plan_tile_info(const fpm_plan_t* plan, int32_t tile, fpm_tile_info* info) {
+fpm_status fpm_plan_tile_info(const fpm_plan_t* plan, int32_t tile, fpm_tile_info* info) try {
   if (!plan || !info || tile < 0 || tile >= (int)plan->tiles.size())
     return fail(FPM_E_ARG, "fpm_plan_tile_info: bad argument");
   const TilePlan& tp = plan->tiles[tile];
@@ -259,9 +258,10 @@ fpm_status fpm_plan_tile_info(const fpm_plan_t* plan, int32_t tile, fpm_tile_inf
   info->reserved = 0;
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_plan_tile_info")
 
 fpm_status fpm_plan_tables(const fpm_plan_t* plan, int32_t tile, int32_t* offsets, int32_t* order,
-                           int32_t* group_of, int32_t* sweep) {
+                           int32_t* group_of, int32_t* sweep) try {
   if (!plan || tile < 0 || tile >= (int)plan->tiles.size())
     return fail(FPM_E_ARG, "fpm_plan_tables: bad argument");
   const TilePlan& tp = plan->tiles[tile];
@@ -271,15 +271,17 @@ fpm_status fpm_plan_tables(const fpm_plan_t* plan, int32_t tile, int32_t* offset
   if (sweep) std::memcpy(sweep, tp.sweep.data(), sizeof(int32_t) * tp.L);
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_plan_tables")
 
-fpm_status fpm_plan_device_bytes(const fpm_plan_t* plan, size_t* bytes) {
+fpm_status fpm_plan_device_bytes(const fpm_plan_t* plan, size_t* bytes) try {
   if (!plan || !bytes) return fail(FPM_E_ARG, "fpm_plan_device_bytes: bad argument");
   *bytes = plan->exec.device_bytes();
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_plan_device_bytes")
 
 fpm_status fpm_stitch(const void* tiles, int32_t rows, int32_t cols, int32_t side,
-                      int32_t overlap, void* out, fpm_mem where, void* hip_stream) {
+                      int32_t overlap, void* out, fpm_mem where, void* hip_stream) try {
   if (!tiles || !out || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_stitch: NULL argument or bad memory kind");
   if (rows < 1 || cols < 1 || side < 2 || side > 65536 || overlap < 0 || 2 * overlap > side ||
@@ -316,9 +318,10 @@ fpm_status fpm_stitch(const void* tiles, int32_t rows, int32_t cols, int32_t sid
   if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_stitch")
 
 fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, float* intensity,
-                       fpm_mem where, void* hip_stream) {
+                       fpm_mem where, void* hip_stream) try {
   if (!plan || !object || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_forward: NULL argument or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
@@ -360,10 +363,11 @@ fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, 
   }
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_forward")
 
 fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem where,
                            void* object_out, void* pupil_out, double* residual_out,
-                           void* hip_stream) {
+                           void* hip_stream) try {
   if (!plan || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_reconstruct: NULL argument or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
@@ -389,8 +393,9 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   if (!hip_ok(ex.run(s, use_graphs()), "reconstruction sweep", &st)) return st;
   return collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
 }
+FPM_ABI_GUARD("fpm_reconstruct")
 
-fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) {
+fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) try {
   if (!plan) return fail(FPM_E_ARG, "fpm_online_begin: NULL plan");
   std::lock_guard<std::mutex> lk(plan->mu);
   const int L = plan->tiles[0].L;
@@ -423,9 +428,10 @@ fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) {
   ex.online_count = 0;
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_online_begin")
 
 fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity, fpm_mem where,
-                           void* hip_stream) {
+                           void* hip_stream) try {
   if (!plan || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_online_push: NULL argument or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
@@ -497,9 +503,10 @@ fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity
   }
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_online_push")
 
 fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, void* pupil_out,
-                             double* residual_out, void* hip_stream) {
+                             double* residual_out, void* hip_stream) try {
   if (!plan || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_online_finish: NULL plan or bad memory kind");
   std::lock_guard<std::mutex> lk(plan->mu);
@@ -529,8 +536,9 @@ fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, 
     return st != FPM_OK ? st : st2;
   return st;
 }
+FPM_ABI_GUARD("fpm_online_finish")
 
-fpm_status fpm_online_abort(fpm_plan_t* plan) {
+fpm_status fpm_online_abort(fpm_plan_t* plan) try {
   if (!plan) return fail(FPM_E_ARG, "fpm_online_abort: NULL plan");
   std::lock_guard<std::mutex> lk(plan->mu);
   Executor& ex = plan->exec;
@@ -546,9 +554,10 @@ fpm_status fpm_online_abort(fpm_plan_t* plan) {
     return st;
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_online_abort")
 
 fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
-                                   fpm_kernel_time* out, void* hip_stream) {
+                                   fpm_kernel_time* out, void* hip_stream) try {
   if (!plan || !intensity || !out) return fail(FPM_E_ARG, "fpm_profile_reconstruct: NULL argument");
   std::lock_guard<std::mutex> lk(plan->mu);
   if (plan->exec.online_count >= 0)
@@ -566,5 +575,6 @@ fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
     return st;
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_profile_reconstruct")
 
 }  // extern "C"

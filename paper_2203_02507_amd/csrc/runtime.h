@@ -1,6 +1,7 @@
 // Executor: device state and the launch sequence of a reconstruction.
 #pragma once
 
+#include <exception>
 #include <string>
 #include <vector>
 
@@ -11,6 +12,17 @@ namespace fpm {
 extern thread_local std::string g_last_error;
 fpm_status fail(fpm_status s, const std::string& msg);
 bool hip_ok(hipError_t e, const char* what, fpm_status* st);
+
+// Handler of the function-try-block around each C ABI entry point that returns
+// a status: an exception thrown by host code (an allocation, a thread start)
+// becomes FPM_E_NOMEM with its message instead of leaving the C boundary.
+#define FPM_ABI_GUARD(name)                                                         \
+  catch (const std::exception& e) {                                                 \
+    return ::fpm::fail(FPM_E_NOMEM, std::string(name) + ": host failure: " + e.what()); \
+  }                                                                                 \
+  catch (...) {                                                                     \
+    return ::fpm::fail(FPM_E_NOMEM, std::string(name) + ": host failure");          \
+  }
 
 struct DevBuf {
   void* p = nullptr;

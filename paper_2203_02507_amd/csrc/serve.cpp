@@ -55,6 +55,9 @@ struct Request {
   // results (host)
   std::vector<float2> obj, pupil;
   std::vector<double> residual;
+  // why the request failed: set by the worker thread, reported by fpm_poll/fpm_wait
+  // (the worker's own last-error message is not visible to the caller's thread)
+  std::string err;
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -449,7 +452,7 @@ void fpm_server_s::run() {
         if (!admit(r, err)) {
           release(r);
           r->status = FPM_E_DEVICE;
-          g_last_error = err;
+          r->err = "admission: " + err;
           cv_done.notify_all();
           continue;
         }
@@ -457,6 +460,7 @@ void fpm_server_s::run() {
           const hipError_t e = finish(r);
           release(r);
           r->status = e == hipSuccess ? FPM_OK : FPM_E_DEVICE;
+          if (e != hipSuccess) r->err = std::string("result copy: ") + hipGetErrorString(e);
           r->stats.finish_s = now_s(t0);
           cv_done.notify_all();
           continue;
@@ -466,16 +470,21 @@ void fpm_server_s::run() {
       batch = active;
     }
     if (batch.empty()) continue;
-    const hipError_t e = tick(batch);
+    hipError_t e;
+    try {
+      e = tick(batch);
+    } catch (const std::exception&) {  // host allocation of the tick's work lists
+      e = hipErrorOutOfMemory;
+    }
     std::lock_guard<std::mutex> lk(mu);
     if (e != hipSuccess) {
       for (Request* r : batch) {
         release(r);
         r->status = FPM_E_DEVICE;
+        r->err = std::string("server tick: ") + hipGetErrorString(e);
       }
       active.clear();
       fatal = FPM_E_DEVICE;
-      g_last_error = std::string("server tick: ") + hipGetErrorString(e);
       cv_done.notify_all();
       continue;
     }
@@ -489,6 +498,10 @@ void fpm_server_s::run() {
         for (double v : r->residual) finite &= std::isfinite(v);
         release(r);
         r->status = fe != hipSuccess ? FPM_E_DEVICE : (finite ? FPM_OK : FPM_E_DIVERGED);
+        if (fe != hipSuccess)
+          r->err = std::string("result copy: ") + hipGetErrorString(fe);
+        else if (!finite)
+          r->err = "residual became non-finite";
         r->stats.finish_s = now_s(t0);
         it = active.erase(it);
         cv_done.notify_all();
@@ -501,7 +514,7 @@ void fpm_server_s::run() {
 
 extern "C" {
 
-fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t** out) {
+fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t** out) try {
   if (!out || max_slots < 1 || max_slots > 65536 || hbm_budget_bytes == 0)
     return fail(FPM_E_ARG, "fpm_server_create: bad argument");
   *out = nullptr;
@@ -537,6 +550,7 @@ fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_ser
   *out = s.release();
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_server_create")
 
 void fpm_server_destroy(fpm_server_t* s) {
   if (!s) return;
@@ -555,7 +569,7 @@ void fpm_server_destroy(fpm_server_t* s) {
 }
 
 fpm_status fpm_submit(fpm_server_t* s, const fpm_tile_desc* tile, const float* intensity,
-                      fpm_mem where, uint64_t* id) {
+                      fpm_mem where, uint64_t* id) try {
   if (!s || !tile || !intensity || !id || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_submit: bad argument");
   std::unique_ptr<Request> r(new (std::nothrow) Request());
@@ -585,6 +599,7 @@ fpm_status fpm_submit(fpm_server_t* s, const fpm_tile_desc* tile, const float* i
   s->cv_work.notify_all();
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_submit")
 
 static fpm_status collect(fpm_server_t* s, std::unique_lock<std::mutex>& lk, uint64_t id,
                           void* object_out, void* pupil_out, double* residual_out,
@@ -610,22 +625,24 @@ static fpm_status collect(fpm_server_t* s, std::unique_lock<std::mutex>& lk, uin
     *stats = r->stats;
     stats->status = st;
   }
-  s->all.erase(it);
+  const std::string why = st == FPM_E_CANCELLED ? std::string("request cancelled")
+                                                : "request failed: " + r->err;
+  s->all.erase(it);  // frees *r
   (void)lk;
-  if (st != FPM_OK)
-    return fail(st, st == FPM_E_CANCELLED ? "request cancelled" : "request failed");
+  if (st != FPM_OK) return fail(st, why);
   return FPM_OK;
 }
 
 fpm_status fpm_poll(fpm_server_t* s, uint64_t id, void* object_out, void* pupil_out,
-                    double* residual_out, fpm_request_stats* stats) {
+                    double* residual_out, fpm_request_stats* stats) try {
   if (!s) return fail(FPM_E_ARG, "fpm_poll: NULL server");
   std::unique_lock<std::mutex> lk(s->mu);
   return collect(s, lk, id, object_out, pupil_out, residual_out, stats);
 }
+FPM_ABI_GUARD("fpm_poll")
 
 fpm_status fpm_wait(fpm_server_t* s, uint64_t id, double timeout_s, void* object_out,
-                    void* pupil_out, double* residual_out, fpm_request_stats* stats) {
+                    void* pupil_out, double* residual_out, fpm_request_stats* stats) try {
   if (!s) return fail(FPM_E_ARG, "fpm_wait: NULL server");
   std::unique_lock<std::mutex> lk(s->mu);
   const auto deadline = std::chrono::steady_clock::now() +
@@ -637,8 +654,9 @@ fpm_status fpm_wait(fpm_server_t* s, uint64_t id, double timeout_s, void* object
   });
   return collect(s, lk, id, object_out, pupil_out, residual_out, stats);
 }
+FPM_ABI_GUARD("fpm_wait")
 
-fpm_status fpm_cancel(fpm_server_t* s, uint64_t id) {
+fpm_status fpm_cancel(fpm_server_t* s, uint64_t id) try {
   if (!s) return fail(FPM_E_ARG, "fpm_cancel: NULL server");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->all.find(id);
@@ -647,5 +665,6 @@ fpm_status fpm_cancel(fpm_server_t* s, uint64_t id) {
   s->cv_work.notify_all();
   return FPM_OK;
 }
+FPM_ABI_GUARD("fpm_cancel")
 
 }  // extern "C"

@@ -95,6 +95,7 @@ def test_small_budget_queues_and_cancel(fpm, orc):
             with pytest.raises(fpm.FpmError) as e:
                 srv.wait(i, d)
             assert e.value.status == fpm.FPM_E_CANCELLED
+            assert "request cancelled" in str(e.value)  # the message reaches the caller's thread
             continue
         _, st = srv.wait(i, d)
         stats.append(st)
