@@ -10,9 +10,12 @@ reconstructed by the oracle one by one and compared element by element
 (relative L2 <= 1e-4 on the object and the pupil); all 256 tiles are checked
 for properties that hold at any size (finite state, residual falling from
 the first to the last iteration), and the sampled tiles of the full batch
-are bitwise those of a plan holding only them.
+are bitwise those of a plan holding only them.  The same batch through the
+MFMA DFT path (split BF16 and FP16) matches the same oracle results on the
+sampled tiles within 1e-3.
 """
 from concurrent.futures import ThreadPoolExecutor
+import dataclasses
 import os
 
 import numpy as np
@@ -23,6 +26,7 @@ import fpm_synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
+TOL_MFMA = 1e-3
 SAMPLE = [0, 137, 255]
 
 
@@ -84,3 +88,11 @@ def test_full_field_sampled_tiles_match_oracle(fpm, orc):
     _, alone = run(fpm, [descs[t] for t in SAMPLE], [stacks[t] for t in SAMPLE])
     for k, t in enumerate(SAMPLE):
         assert all(np.array_equal(a, b) for a, b in zip(alone[k], out[t])), t
+
+    # the MFMA DFT path on the same stacks (the oracle's result does not depend on it)
+    for prec in (1, 2):
+        _, mout = run(fpm, [dataclasses.replace(d, precision=prec) for d in descs], stacks)
+        for t, (o_ref, P_ref, _) in zip(SAMPLE, refs):
+            err, perr = rel(mout[t][0], o_ref), rel(mout[t][1], P_ref)
+            print(f"precision {prec} tile {t}: rel L2 object {err:.3e} pupil {perr:.3e}", flush=True)
+            assert err <= TOL_MFMA and perr <= TOL_MFMA, (prec, t)
