@@ -25,8 +25,13 @@
  *    addresses on the current device; `hip_stream` is a hipStream_t cast to
  *    void* (NULL = the default stream).
  *  - Errors: every call returns an fpm_status; nothing is thrown across the
- *    ABI.  fpm_last_error() gives a thread-local message for the last
- *    non-OK status.  On error no output buffer is written.
+ *    ABI (a host allocation or thread start that fails inside a call
+ *    returns FPM_E_NOMEM).  fpm_last_error() gives a thread-local message
+ *    for the last non-OK status.  A call rejected before it enqueues work
+ *    (FPM_E_ARG, FPM_E_GEOMETRY, FPM_E_STATE, FPM_E_UNSUPPORTED) writes no
+ *    output buffer; after FPM_E_NOMEM, FPM_E_DIVERGED or FPM_E_DEVICE the
+ *    outputs' contents are unspecified (FPM_E_DIVERGED is found once they
+ *    are written).
  */
 #ifndef FPM_H
 #define FPM_H
