@@ -179,6 +179,31 @@ def _ptr(x, where: int):
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
+# element size and accepted dtypes of the C buffer kinds; a complex64 buffer
+# may also be a float32 array of interleaved (re, im) pairs
+_KIND_BYTES = {"f32": 4, "c64": 8, "f64": 8}
+_KIND_NP = {"f32": ("float32",), "c64": ("complex64", "float32"), "f64": ("float64",)}
+
+
+def _buf(x, where: int, kind: str, count: int, what: str):
+    """_ptr, after checking that `x` holds at least `count` elements of the
+    C type `kind`: the library writes and reads exactly that many, so a
+    short or mistyped buffer is refused here, before any call is made."""
+    p = _ptr(x, where)
+    if p is None:
+        return None
+    if torch is not None and isinstance(x, torch.Tensor):
+        dt, nbytes = str(x.dtype).replace("torch.", ""), x.numel() * x.element_size()
+    else:
+        dt, nbytes = str(x.dtype), x.nbytes
+    if dt not in _KIND_NP[kind]:
+        raise TypeError(f"{what}: dtype {dt}, expected {' or '.join(_KIND_NP[kind])}")
+    need = int(count) * _KIND_BYTES[kind]
+    if nbytes < need:
+        raise ValueError(f"{what}: {nbytes} bytes, needs at least {need}")
+    return p
+
+
 def _stream(stream):
     if stream is None:
         if torch is not None and torch.cuda.is_available():
@@ -267,15 +292,19 @@ def fpm_plan(descs: Sequence) -> Plan:
 
 
 def fpm_forward(plan: Plan, obj, pupil, intensity, where: int, stream=None) -> int:
-    return check(lib.fpm_forward(plan.handle, _ptr(obj, where), _ptr(pupil, where),
-                                 _ptr(intensity, where), where, _stream(stream)))
+    return check(lib.fpm_forward(plan.handle, _buf(obj, where, "c64", plan.total_object, "object"),
+                                 _buf(pupil, where, "c64", plan.total_pupil, "pupil"),
+                                 _buf(intensity, where, "f32", plan.total_intensity, "intensity"),
+                                 where, _stream(stream)))
 
 
 def fpm_reconstruct(plan: Plan, intensity, where: int, object_out=None, pupil_out=None,
                     residual_out=None, stream=None) -> int:
-    return check(lib.fpm_reconstruct(plan.handle, _ptr(intensity, where), where,
-                                     _ptr(object_out, where), _ptr(pupil_out, where),
-                                     _ptr(residual_out, where), _stream(stream)))
+    return check(lib.fpm_reconstruct(
+        plan.handle, _buf(intensity, where, "f32", plan.total_intensity, "intensity"), where,
+        _buf(object_out, where, "c64", plan.total_object, "object_out"),
+        _buf(pupil_out, where, "c64", plan.total_pupil, "pupil_out"),
+        _buf(residual_out, where, "f64", plan.total_residual, "residual_out"), _stream(stream)))
 
 
 def fpm_online_begin(plan: Plan, stream=None) -> int:
@@ -286,15 +315,17 @@ def fpm_online_begin(plan: Plan, stream=None) -> int:
 def fpm_online_push(plan: Plan, led: int, intensity, where: int, stream=None) -> int:
     """The tiles' images of LED `led`, float [tile][n][n]; runs that LED's
     update on every tile."""
-    return check(lib.fpm_online_push(plan.handle, led, _ptr(intensity, where), where,
-                                     _stream(stream)))
+    return check(lib.fpm_online_push(plan.handle, led,
+                                     _buf(intensity, where, "f32", plan.total_pupil, "intensity"),
+                                     where, _stream(stream)))
 
 
 def fpm_online_finish(plan: Plan, where: int, object_out=None, pupil_out=None,
                       residual_out=None, stream=None) -> int:
-    return check(lib.fpm_online_finish(plan.handle, where, _ptr(object_out, where),
-                                       _ptr(pupil_out, where), _ptr(residual_out, where),
-                                       _stream(stream)))
+    return check(lib.fpm_online_finish(
+        plan.handle, where, _buf(object_out, where, "c64", plan.total_object, "object_out"),
+        _buf(pupil_out, where, "c64", plan.total_pupil, "pupil_out"),
+        _buf(residual_out, where, "f64", plan.total_residual, "residual_out"), _stream(stream)))
 
 
 def fpm_online_abort(plan: Plan) -> int:
@@ -306,8 +337,9 @@ def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:
     around every launch, chains concurrent): launches, items, summed launch
     durations and the union of the launch intervals."""
     out = (KernelTimeC * len(KERNEL_KINDS))()
-    check(lib.fpm_profile_reconstruct(plan.handle, _ptr(intensity, FPM_MEM_DEVICE), out,
-                                      _stream(stream)))
+    check(lib.fpm_profile_reconstruct(
+        plan.handle, _buf(intensity, FPM_MEM_DEVICE, "f32", plan.total_intensity, "intensity"),
+        out, _stream(stream)))
     return {name: {"launches": out[i].launches, "items": out[i].items,
                    "total_ms": out[i].total_ms, "busy_ms": out[i].busy_ms}
             for i, name in enumerate(KERNEL_KINDS)}
@@ -317,7 +349,12 @@ def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where:
                stream=None) -> int:
     """Sec. 3.1 Eq. (1): tiles complex64 [rows][cols][side][side] -> out
     complex64 [H][W] (see include/fpm.h)."""
-    return check(lib.fpm_stitch(_ptr(tiles, where), rows, cols, side, overlap, _ptr(out, where),
+    # sizes are checked for a geometry the library accepts; it rejects the rest itself
+    ok = rows > 0 and cols > 0 and side > 0 and 0 <= overlap < side
+    H, W = stitched_shape(rows, cols, side, overlap) if ok else (0, 0)
+    count = rows * cols * side * side if ok else 0
+    return check(lib.fpm_stitch(_buf(tiles, where, "c64", count, "tiles"), rows, cols, side,
+                                overlap, _buf(out, where, "c64", H * W, "out"),
                                 where, _stream(stream)))
 
 
@@ -387,7 +424,9 @@ class Server:
     def submit(self, desc, intensity, where: int) -> int:
         rid = C.c_uint64()
         cd = to_c_desc(desc)
-        check(lib.fpm_submit(self._h, C.byref(cd), _ptr(intensity, where), where, C.byref(rid)))
+        count = desc.led_rows * desc.led_cols * desc.n * desc.n
+        check(lib.fpm_submit(self._h, C.byref(cd), _buf(intensity, where, "f32", count, "intensity"),
+                             where, C.byref(rid)))
         self._keep[rid.value] = (cd, intensity)
         return rid.value
 
