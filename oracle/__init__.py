@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-fopenmp",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -72,6 +72,7 @@ def lib():
         gp = C.POINTER(Geom)
         L.orc_fft1.argtypes = [dp, C.c_int32, C.c_int32]
         L.orc_fft2.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32]
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_support.argtypes = [gp, up8]
         L.orc_support.restype = C.c_int32
         L.orc_pupil_init.argtypes = [gp, dp]
@@ -90,6 +91,11 @@ def lib():
         L.orc_reconstruct_online.restype = C.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> None:
+    """Threads for the oracle's line transforms (results do not depend on it)."""
+    lib().orc_set_threads(int(k))
 
 
 def _p(a, t):

@@ -37,13 +37,19 @@ static void fft_rec(const double *in, int istride, double *out, int n,
   int m = n / p;
   for (int r = 0; r < p; ++r)
     fft_rec(in + 2 * r * istride, istride * p, out + 2 * r * m, m, w, wstep * p, wn);
-  double *tmp = (double *)malloc(sizeof(double) * 2 * p);
+  /* the p outputs of one butterfly; small radices (every size used here
+   * factors into 2, 3 and 5) stay on the stack */
+  double tmp_small[2 * 8];
+  double *tmp = p <= 8 ? tmp_small : (double *)malloc(sizeof(double) * 2 * p);
   for (int k = 0; k < m; ++k) {
     for (int s = 0; s < p; ++s) {
       double ar = 0.0, ai = 0.0;
       for (int r = 0; r < p; ++r) {
-        long e = ((long)r * (long)(k + m * s)) % n;   /* exponent of W_n */
-        const double *t = w + 2 * ((e * wstep) % wn);
+        /* exponent of W_n: r (k + m s) mod n, with r (k + m s) < p n; the
+         * table holds W_wn^j and W_n = W_wn^wstep (wstep * n = wn) */
+        long e = (long)r * (long)(k + m * s);
+        while (e >= n) e -= n;
+        const double *t = w + 2 * (e * wstep);
         double yr = out[2 * (r * m + k)], yi = out[2 * (r * m + k) + 1];
         ar += yr * t[0] - yi * t[1];
         ai += yr * t[1] + yi * t[0];
@@ -56,7 +62,7 @@ static void fft_rec(const double *in, int istride, double *out, int n,
       out[2 * (k + m * s) + 1] = tmp[2 * s + 1];
     }
   }
-  free(tmp);
+  if (tmp != tmp_small) free(tmp);
 }
 
 static double *twiddles(int n, int sign) {
@@ -86,29 +92,43 @@ void orc_fft1(double *z, int32_t n, int32_t sign) {
   free(w);
 }
 
+/* Worker threads for the line transforms of orc_fft2 (default 1).  The
+ * lines of a 2-D transform are independent, and each line is computed the
+ * same way whichever thread runs it, so the result does not depend on this
+ * count. */
+static int g_threads = 1;
+
+void orc_set_threads(int32_t k) { g_threads = k < 1 ? 1 : k; }
+
 void orc_fft2(double *z, int32_t rows, int32_t cols, int32_t sign) {
   int sg = sign < 0 ? -1 : 1;
   int mx = rows > cols ? rows : cols;
-  double *buf = (double *)malloc(sizeof(double) * 2 * mx);
-  double *line = (double *)malloc(sizeof(double) * 2 * mx);
   double *wc = twiddles(cols, sg);
-  for (int r = 0; r < rows; ++r) fft_line(z + 2 * (size_t)r * cols, cols, sign, wc, buf);
-  free(wc);
   double *wr = twiddles(rows, sg);
-  for (int c = 0; c < cols; ++c) {
-    for (int r = 0; r < rows; ++r) {
-      line[2 * r] = z[2 * ((size_t)r * cols + c)];
-      line[2 * r + 1] = z[2 * ((size_t)r * cols + c) + 1];
+  /* rows first, then columns */
+#pragma omp parallel num_threads(g_threads) if (g_threads > 1)
+  {
+    double *buf = (double *)malloc(sizeof(double) * 2 * mx);
+    double *line = (double *)malloc(sizeof(double) * 2 * mx);
+#pragma omp for schedule(static)
+    for (int r = 0; r < rows; ++r) fft_line(z + 2 * (size_t)r * cols, cols, sign, wc, buf);
+#pragma omp for schedule(static)
+    for (int c = 0; c < cols; ++c) {
+      for (int r = 0; r < rows; ++r) {
+        line[2 * r] = z[2 * ((size_t)r * cols + c)];
+        line[2 * r + 1] = z[2 * ((size_t)r * cols + c) + 1];
+      }
+      fft_line(line, rows, sign, wr, buf);
+      for (int r = 0; r < rows; ++r) {
+        z[2 * ((size_t)r * cols + c)] = line[2 * r];
+        z[2 * ((size_t)r * cols + c) + 1] = line[2 * r + 1];
+      }
     }
-    fft_line(line, rows, sign, wr, buf);
-    for (int r = 0; r < rows; ++r) {
-      z[2 * ((size_t)r * cols + c)] = line[2 * r];
-      z[2 * ((size_t)r * cols + c) + 1] = line[2 * r + 1];
-    }
+    free(line);
+    free(buf);
   }
   free(wr);
-  free(line);
-  free(buf);
+  free(wc);
 }
 
 /* Centring shift by half the size on both axes (even sizes: its own inverse). */

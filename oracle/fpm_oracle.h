@@ -53,6 +53,9 @@ enum { ORC_SEQUENTIAL = 0, ORC_LED_GROUPS = 1, ORC_GROUP_ORDER = 2 };
  * sign = -1 forward (unnormalised), +1 inverse (scaled by 1/size). */
 void orc_fft1(double *z, int32_t n, int32_t sign);
 void orc_fft2(double *z, int32_t rows, int32_t cols, int32_t sign);
+/* Threads for the independent line transforms of orc_fft2 (default 1; the
+ * results do not depend on it). */
+void orc_set_threads(int32_t k);
 
 /* Frequency support of the objective: returns |D0|, fills mask[n*n]. */
 int32_t orc_support(const orc_geom *g, uint8_t *mask);

@@ -16,4 +16,7 @@ def pytest_configure(config):
 def orc():
     import oracle
     oracle.lib()
+    # the oracle's 2-D transforms split their lines over threads; results do
+    # not depend on the count (at most the 16 host cores of one GPU's share)
+    oracle.set_threads(min(16, os.cpu_count() or 1))
     return oracle

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import fpm_synth
+from parity import TOL_WIN_MFMA, check_windows
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +77,9 @@ def test_results_do_not_depend_on_chains_or_graph(fpm, orc, monkeypatch):
         d = descs[t]
         r = orc.reconstruct(d, Is[t], schedule=0 if d.schedule == 3 else d.schedule)
         assert r.status == 0
-        err = rel(ref[t][0], orc.spectrum_to_object(d, r.S))
+        o_ref = orc.spectrum_to_object(d, r.S)
+        err = rel(ref[t][0], o_ref)
         print(f"tile {t} n {d.n} schedule {d.schedule} precision {d.precision}: rel L2 {err:.3e}")
         assert err <= (1e-4 if d.precision == 0 else 1e-3), t
+        check_windows(orc, d, ref[t][0], o_ref,
+                      1e-3 if d.precision == 0 else TOL_WIN_MFMA[d.precision], f"tile {t}")

@@ -12,7 +12,9 @@ for properties that hold at any size (finite state, residual falling from
 the first to the last iteration), and the sampled tiles of the full batch
 are bitwise those of a plan holding only them.  The same batch through the
 MFMA DFT path (split BF16 and FP16) matches the same oracle results on the
-sampled tiles within 1e-3.
+sampled tiles within 1e-3.  Every sampled result is also bounded on each LED's
+support window and on the dark-field-only region of the spectrum (parity.py):
+1e-3 for FP32, TOL_WIN_MFMA for the MFMA forms.
 """
 from concurrent.futures import ThreadPoolExecutor
 import dataclasses
@@ -22,11 +24,13 @@ import numpy as np
 import pytest
 
 import fpm_synth
+from parity import TOL_WIN_MFMA, check_windows
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
 TOL_MFMA = 1e-3
+TOL_WIN = 1e-3
 SAMPLE = [0, 137, 255]
 
 
@@ -82,6 +86,7 @@ def test_full_field_sampled_tiles_match_oracle(fpm, orc):
         err, perr = rel(o, o_ref), rel(P, P_ref)
         print(f"tile {t}: rel L2 object {err:.3e} pupil {perr:.3e}", flush=True)
         assert err <= TOL and perr <= TOL, t
+        check_windows(orc, descs[t], o, o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
     # the sampled tiles alone: the same bits as in the full batch
@@ -96,3 +101,5 @@ def test_full_field_sampled_tiles_match_oracle(fpm, orc):
             err, perr = rel(mout[t][0], o_ref), rel(mout[t][1], P_ref)
             print(f"precision {prec} tile {t}: rel L2 object {err:.3e} pupil {perr:.3e}", flush=True)
             assert err <= TOL_MFMA and perr <= TOL_MFMA, (prec, t)
+            check_windows(orc, descs[t], mout[t][0], o_ref, TOL_WIN_MFMA[prec],
+                          f"precision {prec} tile {t}")

@@ -7,11 +7,13 @@ import numpy as np
 import pytest
 
 import fpm_synth
+from parity import TOL_WIN_MFMA, check_windows
 
 pytestmark = pytest.mark.gpu
 
 TOL_MFMA = 1e-3
 TOL_FP32 = 1e-4
+TOL_WIN_FP32 = 1e-3
 PRECS = [fpm_synth.PREC_MFMA_BF16X3, fpm_synth.PREC_MFMA_FP16]
 # Residual histories: residual = sum(|psi| - sqrt I)^2 / sum I, and near
 # convergence |psi| - sqrt I is ~3 % of sqrt I, so a relative error eps in
@@ -62,6 +64,7 @@ def test_single_tile_mfma_matches_oracle(fpm, orc, prec):
           f"pupil {rel(P, P_ref):.3e}")
     assert err <= TOL_MFMA
     assert rel(P, P_ref) <= TOL_MFMA
+    check_windows(orc, td.desc, o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec}")
     assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9)
 
 
@@ -85,6 +88,7 @@ def test_full_field_tiles_mfma_match_oracle(fpm, orc, prec):
     for t, ((o, P, r), (o_ref, P_ref, r_ref)) in enumerate(zip(out, refs)):
         assert errs[t] <= TOL_MFMA, t
         assert rel(P, P_ref) <= TOL_MFMA, t
+        check_windows(orc, descs[t], o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec} tile {t}")
         assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9), t
 
 
@@ -111,6 +115,9 @@ def test_mixed_precisions_and_sizes_in_one_plan(fpm, orc):
         err = rel(out[t][0], o_ref)
         print(f"tile {t} n {d.n} precision {d.precision}: rel L2 {err:.3e}")
         assert err <= (TOL_FP32 if d.precision == 0 else TOL_MFMA), t
+        check_windows(orc, d, out[t][0], o_ref,
+                      TOL_WIN_FP32 if d.precision == 0 else TOL_WIN_MFMA[d.precision],
+                      f"tile {t} precision {d.precision}")
     alone = run_gpu(fpm, [descs[0]], [Is[0]])[0]
     assert all(np.array_equal(a, b) for a, b in zip(alone, out[0]))
 
@@ -138,3 +145,4 @@ def test_mfma_edge_cases(fpm, orc):
             assert np.all(o == 0), t
         else:
             assert rel(o, o_ref) <= TOL_MFMA, t
+            check_windows(orc, dd, o, o_ref, TOL_WIN_MFMA[dd.precision], f"edge case {t}")

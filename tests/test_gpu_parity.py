@@ -3,16 +3,21 @@ oracle on the same seeded inputs.
 
 Tolerance: relative L2 error <= 1e-4 on the reconstructed complex object
 (FP32 path), as the FP32 target of the method's accuracy budget states; the
-integer tables are compared bit for bit in test_plan_cpu.py.
+integer tables are compared bit for bit in test_plan_cpu.py.  The recovered
+spectrum is also bounded on every LED's support window and on the region only
+dark-field LEDs reach (relative L2 <= 1e-3 each, see parity.py), which the
+whole-object measure cannot see.
 """
 import numpy as np
 import pytest
 
 import fpm_synth
+from parity import check_windows
 
 pytestmark = pytest.mark.gpu
 
 TOL_OBJ = 1e-4
+TOL_WIN = 1e-3
 
 
 def rel(a, b):
@@ -82,6 +87,7 @@ def test_single_tile_sequential_matches_oracle(fpm, orc):
     err = rel(o, o_ref)
     print("single-tile rel L2 object error vs oracle:", err)
     assert err <= TOL_OBJ
+    check_windows(orc, td.desc, o, o_ref, TOL_WIN, "single tile")
     assert rel(P, P_ref) <= TOL_OBJ
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
@@ -104,6 +110,7 @@ def test_multi_tile_schedules_match_oracle(fpm, orc, schedule, pupil):
         err = rel(o, o_ref)
         print(f"tile {t} schedule {schedule} pupil {pupil}: rel L2 {err:.3e}")
         assert err <= TOL_OBJ
+        check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
         assert rel(P, P_ref) <= TOL_OBJ
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
@@ -172,6 +179,7 @@ def test_mixed_sizes_and_edge_cases(fpm, orc):
             assert np.all(o == 0), t
         else:
             assert rel(o, o_ref) <= TOL_OBJ, t
+            check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
@@ -188,6 +196,7 @@ def test_large_board_far_leds_match_oracle(fpm, orc):
     assert np.all(np.isfinite(o)) and np.all(np.isfinite(r))
     o_ref, P_ref, r_ref = oracle_run(orc, d, I)
     assert rel(o, o_ref) <= TOL_OBJ
+    check_windows(orc, d, o, o_ref, TOL_WIN, "21x21 board")
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
 
@@ -218,6 +227,53 @@ def test_uneven_batch_matches_oracle(fpm, orc):
         err = rel(o, o_ref)
         print(f"tile {t} n {d.n} grid {d.led_rows} up {d.upsample}: rel L2 {err:.3e}")
         assert err <= TOL_OBJ, t
+        check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
+        assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
+
+
+def _uneven_tiles(indices):
+    tds = fpm_synth.uneven_batch(only=indices)
+    for td in tds:
+        d = td.desc
+        for up in td.up_candidates:
+            d.upsample = up
+            if fpm_synth_offsets_ok(d):
+                break
+    return tds
+
+
+def fpm_synth_offsets_ok(d):
+    import oracle
+    return oracle.offsets(d)[0] == 0
+
+
+@pytest.mark.timeout(900)
+def test_uneven_tiles_at_drawn_iterations_match_oracle(fpm, orc):
+    """Tiles of the 512-tile uneven batch at the iteration counts they drew
+    (no cap), in one plan: a 256-px tile on a 21x21 board (441 LEDs, 5x
+    upsampling, 21 iterations), a 96-px tile on 13x13 LEDs (29 iterations)
+    and a 64-px tile on 13x13 LEDs (5x upsampling, 28 iterations).  Far dark-field windows
+    of a large board hold ~1e-10 of the energy; late iterations there are
+    where single precision runs out first."""
+    tds = _uneven_tiles([95, 22, 11])
+    got = sorted((td.desc.n, td.desc.led_rows, td.desc.iterations) for td in tds)
+    assert got == [(64, 13, 28), (96, 13, 29), (256, 21, 21)], got
+    descs, Is = [], []
+    for td in tds:
+        _, _, I = orc.synthesize(td)
+        descs.append(td.desc)
+        Is.append(I)
+    _, out = run_gpu(fpm, descs, Is)
+    for t, d in enumerate(descs):
+        o, P, r = out[t]
+        assert np.all(np.isfinite(o)) and np.all(np.isfinite(r)), t
+        o_ref, P_ref, r_ref = oracle_run(orc, d, Is[t])
+        err = rel(o, o_ref)
+        print(f"tile n {d.n} grid {d.led_rows} up {d.upsample} iters {d.iterations}: "
+              f"rel L2 {err:.3e}, pupil {rel(P, P_ref):.3e}")
+        assert err <= TOL_OBJ, t
+        assert rel(P, P_ref) <= TOL_OBJ, t
+        check_windows(orc, d, o, o_ref, TOL_WIN, f"n {d.n}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
@@ -310,4 +366,5 @@ def test_pipelined_equals_sequential_bitwise(fpm, orc, pupil):
     for t, d in enumerate(descs):
         o_ref, _, r_ref = oracle_run(orc, d, Is[t])
         assert rel(pip[t][0], o_ref) <= TOL_OBJ
+        check_windows(orc, d, pip[t][0], o_ref, TOL_WIN, f"pipelined tile {t}")
         assert np.allclose(pip[t][2], r_ref, rtol=1e-4, atol=1e-9)
