@@ -123,29 +123,130 @@ def mfma_flops_per_update(desc, prec):
     return steps * 4 * 2 * 32 * 32 * 16 * PREC_TERMS[prec], dense * PREC_TERMS[prec]
 
 
-def cpu_baseline(n_tiles: int = 16):
-    """FP64 oracle on a bounded sample: the first `n_tiles` tiles of the
-    same workload, one iteration each, one tile per host thread (at most 16,
-    the host share of one GPU)."""
+def host_cpu():
+    """The host the oracle runs on: logical CPUs, those this process may use,
+    and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count() or 1, "usable": usable, "model": model}
+
+
+def rel_l2(a, b) -> float:
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def small_uneven_tiles(fpm, count: int, max_updates: int = 2500):
+    """The first `count` tiles of the uneven workload's draw (n <= 128, at
+    most `max_updates` updates each) whose geometry the library accepts."""
+    import fpm_synth
+    out = []
+    for td in fpm_synth.uneven_batch(T=512, sizes=(64, 96, 128, 256)):
+        d = td.desc
+        if d.n > 128 or d.led_rows * d.led_cols * d.iterations > max_updates:
+            continue
+        if pick_upsample(fpm, td):
+            out.append(td)
+        if len(out) == count:
+            break
+    return out
+
+
+def cpu_baseline(fpm, n_tiles: int = 16, threads_cap: int = 16):
+    """The FP64 oracle timed on a bounded sample of the benchmark's workload:
+    the first `n_tiles` full-field tiles for all their iterations, one tile
+    per host thread (the usable host CPUs, at most `threads_cap`: the host
+    share of one GPU).  Its results are also the reference for the accuracy
+    of every GPU form reported beside the throughput, computed here, outside
+    every timed region, on the same seeded stacks (the oracle's forward model
+    with shot noise): the FP32 path and each MFMA precision on these tiles,
+    two small tiles of the uneven workload run as one batched plan, and two
+    requests (FP32 and BF16x3) through the server."""
     from concurrent.futures import ThreadPoolExecutor
+    import dataclasses
+    import numpy as np
+    import torch
     import fpm_synth
     import oracle
 
+    host = host_cpu()
+    threads = max(1, min(n_tiles, host["usable"], threads_cap))
+    oracle.set_threads(1)
     tds = fpm_synth.full_fov_tiles(only=list(range(n_tiles)))
-    threads = max(1, min(n_tiles, os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(threads) as ex:
-        inputs = list(ex.map(lambda td: oracle.synthesize(td, z_range=20.0)[2], tds))
+        stacks = list(ex.map(lambda td: oracle.synthesize(td, z_range=20.0)[2], tds))
+    descs = [td.desc for td in tds]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
-        res = list(ex.map(lambda a: oracle.reconstruct(a[0].desc, a[1], iterations=1),
-                          zip(tds, inputs)))
+        res = list(ex.map(lambda a: oracle.reconstruct(a[0], a[1]), zip(descs, stacks)))
     wall = time.perf_counter() - t0
     assert all(r.status == 0 for r in res)
-    updates = n_tiles * tds[0].desc.L
-    return {"value": round(updates / wall, 2), "unit": "updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_tiles} tiles x 1 iteration x 225 LEDs of the 128-px full-field "
-                      f"workload ({updates} updates, {wall:.1f} s wall)"}
+    updates = sum(d.led_rows * d.led_cols * d.iterations for d in descs)
+    refs = [(oracle.spectrum_to_object(d, r.S), r.P) for d, r in zip(descs, res)]
+    log(f"cpu baseline: {updates} oracle updates in {wall:.1f} s on {threads} threads")
+
+    def gpu_run(ds, Is):
+        plan = fpm.Plan(ds)
+        I = torch.from_numpy(np.concatenate([x.reshape(-1) for x in Is])).cuda()
+        obj, pup, res_d = fpm.device_buffers(plan)
+        fpm.fpm_reconstruct(plan, I, fpm.FPM_MEM_DEVICE, obj, pup, res_d)
+        torch.cuda.synchronize()
+        return fpm.split_tiles(plan, obj.cpu().numpy(), pup.cpu().numpy(), res_d.cpu().numpy())
+
+    acc = {}
+    for prec, name in ((0, "fp32_fft"), (1, "mfma_bf16x3"), (2, "mfma_fp16")):
+        out = gpu_run([dataclasses.replace(d, precision=prec) for d in descs], stacks)
+        eo = [rel_l2(o, r[0]) for (o, _, _), r in zip(out, refs)]
+        ep = [rel_l2(p, r[1]) for (_, p, _), r in zip(out, refs)]
+        acc[name] = {"tiles": n_tiles, "object_max": float(f"{max(eo):.3e}"),
+                     "object_mean": float(f"{sum(eo) / len(eo):.3e}"),
+                     "pupil_max": float(f"{max(ep):.3e}"),
+                     "tolerance": 1e-4 if prec == 0 else 1e-3}
+
+    # uneven workload (batched plan) and served requests, small samples
+    small = small_uneven_tiles(fpm, 4)
+    ud = [td.desc for td in small[:2]]
+    uI = [oracle.synthesize(td)[2] for td in small[:2]]
+    sd = [dataclasses.replace(small[2].desc, precision=0),
+          dataclasses.replace(small[3].desc, precision=1)]
+    sI = [oracle.synthesize(td)[2] for td in small[2:4]]
+    with ThreadPoolExecutor(4) as ex:
+        r_all = list(ex.map(lambda a: oracle.reconstruct(a[0], a[1]), zip(ud + sd, uI + sI)))
+    ref_all = [oracle.spectrum_to_object(d, r.S) for d, r in zip(ud + sd, r_all)]
+    out_u = gpu_run(ud, uI)
+    acc["uneven_batch"] = {
+        "tiles": [f"n={d.n} {d.led_rows}x{d.led_cols} LEDs {d.iterations} it" for d in ud],
+        "object": [float(f"{rel_l2(o[0], r):.3e}") for o, r in zip(out_u, ref_all[:2])],
+        "tolerance": 1e-4}
+    srv = fpm.Server(1 << 30, max_slots=8)
+    ids = [srv.submit(d, torch.from_numpy(I.reshape(-1)).cuda(), fpm.FPM_MEM_DEVICE)
+           for d, I in zip(sd, sI)]
+    served = [srv.wait(i, d)[0] for i, d in zip(ids, sd)]
+    srv.close()
+    acc["serving"] = {
+        "requests": [f"n={d.n} {d.led_rows}x{d.led_cols} LEDs {d.iterations} it "
+                     f"{'fp32_fft' if d.precision == 0 else 'mfma_bf16x3'}" for d in sd],
+        "object": [float(f"{rel_l2(o[0], r):.3e}") for o, r in zip(served, ref_all[2:])],
+        "tolerance": [1e-4, 1e-3]}
+    baseline = {"value": round(updates / wall, 2), "unit": "updates/s", "cores": threads,
+                "kind": "oracle",
+                "sample": f"{n_tiles} tiles x {descs[0].iterations} iterations x 225 LEDs of "
+                          f"the 128-px full-field workload ({updates} updates, {wall:.1f} s "
+                          f"wall), one tile per thread",
+                "host": host}
+    return baseline, acc
 
 
 def pick_upsample(fpm, td):
@@ -403,8 +504,23 @@ def uneven_bench(fpm, T: int, steps: int, warmup: int, sample: int = 16):
         return e0.elapsed_time(e1) / k
 
     ms = timed(plan, I, steps)
+    r = res.cpu().numpy()
+    if not all(math.isfinite(x) for x in r):
+        raise SystemExit("uneven batch: non-finite residual")
     prof = fpm.fpm_profile_reconstruct(plan, I)
     torch.cuda.synchronize()
+    # algorithmic HBM bytes of all update launches (per update: the intensity
+    # image read, the spectrum support read and written) over the time at
+    # least one update launch ran
+    alg_bytes = sum(i.L * i.iterations * (4 * i.n * i.n + 16 * i.support_count)
+                    for i in plan.infos)
+    upd = prof["update"]
+    achieved = alg_bytes / (upd["busy_ms"] / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "update kernels of every tile size", "algorithmic_bytes": alg_bytes,
+            "busy_ms": round(upd["busy_ms"], 3),
+            "frac_whole_step": round(alg_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     by_n = {}
     for i in plan.infos:
         b = by_n.setdefault(str(i.n), {"tiles": 0, "updates": 0})
@@ -425,6 +541,7 @@ def uneven_bench(fpm, T: int, steps: int, warmup: int, sample: int = 16):
                                   info.L * info.n * info.n], 1)
     return {"tiles": len(tds), "updates_per_step": updates, "ms_per_step": round(ms, 3),
             "value": round(updates / (ms / 1e3), 1), "unit": "updates/s", "by_n": by_n,
+            "roofline": roof,
             "kernel_ms": {k: round(v["total_ms"], 3) for k, v in prof.items()},
             "update_launches": prof["update"]["launches"],
             "batching_gain": {"tiles": ns, "updates": sub_updates,
@@ -433,19 +550,24 @@ def uneven_bench(fpm, T: int, steps: int, warmup: int, sample: int = 16):
                               "speedup": round(ms_single / ms_batched, 2)}}
 
 
-def serving_bench(fpm, n_req: int = 48, loads=(0.5, 0.8, 0.95), seed: int = 5):
+def serving_bench(fpm, pool: int = 96, warmup: int = 200, measured: int = 1000,
+                  loads=(0.5, 0.8, 0.95), seed: int = 5):
     """Requests shaped like single uneven tiles (64-256 px, 9x9..21x21 LEDs,
     5..30 iterations; precision flags 50 % FP32, 25 % BF16x3, 25 % FP16 on
-    the sizes the MFMA form runs) arriving as a Poisson stream at each of
-    `loads` x the saturated request rate measured closed-loop; p50/p99
-    latency and sustained updates/s per load."""
+    the sizes the MFMA form runs), `pool` distinct ones cycled in a seeded
+    order into `warmup` + `measured` submissions.  The saturated request rate
+    comes from the measured part of a closed-loop run (all submitted at
+    once); then, for each of `loads` x that rate, an open-loop Poisson
+    stream of the same submissions: p50/p99 latency over the measured
+    requests (the warm-up ones fill the server first and are not counted)
+    and the sustained updates/s over them."""
     import numpy as np
     import torch
     import fpm_synth
 
     reqs = []
     mix_rng = np.random.default_rng(seed)
-    for td in fpm_synth.uneven_batch(T=4 * n_req, workload=4, sizes=(64, 96, 128, 256)):
+    for td in fpm_synth.uneven_batch(T=4 * pool, workload=4, sizes=(64, 96, 128, 256)):
         d = td.desc
         if d.n <= 128:
             d.precision = int(mix_rng.choice([0, 0, 1, 2]))
@@ -468,54 +590,59 @@ def serving_bench(fpm, n_req: int = 48, loads=(0.5, 0.8, 0.95), seed: int = 5):
         gen.manual_seed(seed + len(reqs))
         I = torch.poisson(I.clamp_min(0) * c, generator=gen) / c
         reqs.append((d, I.contiguous()))
-        if len(reqs) == n_req:
+        if len(reqs) == pool:
             break
     torch.cuda.synchronize()
+    total = warmup + measured
+    order = np.random.default_rng(seed + 1).integers(0, len(reqs), size=total)
+    seq = [reqs[k] for k in order]
     budget = int(0.5 * torch.cuda.mem_get_info()[0])
-    # closed loop: everything at once -> saturated request rate
     srv = fpm.Server(budget, max_slots=256)
-    t0 = time.perf_counter()
-    ids = [srv.submit(d, I, fpm.FPM_MEM_DEVICE) for d, I in reqs]
-    for i, (d, _) in zip(ids, reqs):
-        srv.wait(i, d)
-    t_sat = time.perf_counter() - t0
-    srv.close()
-    sat_updates = sum(d.L * d.iterations for d, _ in reqs) / t_sat
+
+    def collect(ids):
+        stats = [srv.wait(i, d)[1] for i, (d, _) in zip(ids, seq)]
+        return stats[warmup:]
+
+    # closed loop: everything at once -> saturated request rate
+    ids = [srv.submit(d, I, fpm.FPM_MEM_DEVICE) for d, I in seq]
+    st = collect(ids)
+    first = min(x.submit_s for x in st)
+    span = max(x.finish_s for x in st) - min(x.admit_s for x in st)
+    sat_req = measured / span
+    sat_updates = sum(x.updates for x in st) / span
+    log(f"serving closed loop: {total} requests, {sat_req:.1f} requests/s, "
+        f"{sat_updates / 1e6:.3f} M updates/s over the measured {measured}")
     by_load = {}
     for ld in loads:
-        rate = ld * len(reqs) / t_sat
-        # open loop: Poisson arrivals at `rate`
-        rng = np.random.default_rng(seed)
-        gaps = rng.exponential(1.0 / rate, size=len(reqs))
-        srv = fpm.Server(budget, max_slots=256)
+        rate = ld * sat_req
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=total)
         start = time.perf_counter()
         due = start
         ids = []
-        for (d, I), g in zip(reqs, gaps):
+        for (d, I), g in zip(seq, gaps):
             due += g
             while time.perf_counter() < due:
                 time.sleep(min(1e-3, max(0.0, due - time.perf_counter())))
             ids.append(srv.submit(d, I, fpm.FPM_MEM_DEVICE))
-        lat, first, last, upd = [], None, None, 0
-        for i, (d, _) in zip(ids, reqs):
-            _, st = srv.wait(i, d)
-            lat.append(st.finish_s - st.submit_s)
-            first = st.submit_s if first is None else min(first, st.submit_s)
-            last = st.finish_s if last is None else max(last, st.finish_s)
-            upd += st.updates
-        srv.close()
-        lat = np.array(lat)
+        st = collect(ids)
+        lat = np.array([x.finish_s - x.submit_s for x in st])
+        first = min(x.submit_s for x in st)
+        last = max(x.finish_s for x in st)
         by_load[str(ld)] = {
             "arrival_rate_per_s": round(rate, 2),
             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-            "sustained_updates_per_s": round(upd / (last - first), 1)}
-    return {"requests": len(reqs), "saturated_updates_per_s": round(sat_updates, 1),
-            "by_load": by_load,
+            "sustained_updates_per_s": round(sum(x.updates for x in st) / (last - first), 1)}
+        log(f"serving load {ld}: " + json.dumps(by_load[str(ld)]))
+    srv.close()
+    return {"distinct_requests": len(reqs), "warmup_requests": warmup,
+            "measured_requests": measured, "saturated_requests_per_s": round(sat_req, 2),
+            "saturated_updates_per_s": round(sat_updates, 1), "by_load": by_load,
             "mix": "64-256 px tiles, 81-441 LEDs, 5-30 iterations, precision 50 % FP32, "
-                   "25 % BF16x3, 25 % FP16 (FP32 for 256 px)",
-            "precisions": {str(p): sum(1 for d, _ in reqs if d.precision == p)
-                           for p in (0, 1, 2)}}
+                   "25 % BF16x3, 25 % FP16 (FP32 for 256 px, which the MFMA form does not run)",
+            "precisions": {str(p): int(sum(1 for d, _ in seq[warmup:] if d.precision == p))
+                           for p in (0, 1, 2)},
+            "budget_bytes": budget}
 
 
 def main():
@@ -686,7 +813,9 @@ def main():
     if not args.no_serving:
         serving = serving_bench(fpm)
         log("serving: " + json.dumps(serving))
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    cpu, accuracy = (None, None) if args.no_cpu_baseline else cpu_baseline(fpm)
+    if accuracy is not None:
+        log("accuracy vs FP64 oracle: " + json.dumps(accuracy))
     info = plan.infos[0]
     out = {
         "metric": "LED-tile updates/sec (FP32 vs MFMA DFT) + p50/p99 request latency",
@@ -713,6 +842,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rel_l2_vs_oracle": accuracy,
         "mfma": mfma,
         "stitch": stitch,
         "single_tile": single,

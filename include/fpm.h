@@ -199,7 +199,11 @@ fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
  * The plan's tiles run as independent chains on streams of the library's
  * own, forked from `hip_stream` and joined back into it with events, so the
  * work is ordered on `hip_stream` as one operation; FPM_CHAINS=1..4 sets the
- * number of chains. */
+ * number of chains.  Calls on one plan share its device state: a call on a
+ * stream other than the previous call's first waits (on the device, through
+ * an event) for that call's work, so calls on one plan never overlap,
+ * whatever streams they come on; a call on the previous call's stream waits
+ * for nothing. */
 fpm_status fpm_reconstruct(fpm_plan_t *plan, const float *intensity, fpm_mem where,
                            void *object_out, void *pupil_out, double *residual_out,
                            void *hip_stream);
@@ -239,6 +243,36 @@ fpm_status fpm_online_push(fpm_plan_t *plan, int32_t led, const float *intensity
 fpm_status fpm_online_finish(fpm_plan_t *plan, fpm_mem where, void *object_out,
                              void *pupil_out, double *residual_out, void *hip_stream);
 fpm_status fpm_online_abort(fpm_plan_t *plan);
+
+/* Defocus distance of each sub-region, estimated before its reconstruction
+ * from its bright-field images (Sec. 3.4 Fig. 7b offline strategy, at least
+ * nine bright-field images; Sec. 2.2: each sub-region has its own defocus).
+ * Per tile: the bright-field LEDs are those whose window's zero-frequency
+ * bin (n/2 - drow, n/2 - dcol) lies in the support disc D0 (FPM_E_GEOMETRY
+ * if fewer than nine); the search runs on the smallest centred block of the
+ * LED grid that holds them all (rows and columns of the grid's parity).
+ * For each candidate z = z_lo + k z_step <= z_hi the block is reconstructed
+ * with the pupil fixed at D0 H_z, LED groups, `iterations` iterations, and
+ * scored by its last residual; all candidates of all tiles run as one
+ * batched reconstruction.  z is the vertex of the parabola through the best
+ * score and its two neighbours (the grid point at an end of the grid or
+ * where the three scores are not convex).
+ *   tiles      ntiles descriptors; defocus_um, iterations, pupil_update,
+ *              schedule and precision are not used.
+ *   intensity  float [tile][L][n][n] (grid LED order), `where` host or
+ *              device; host data are validated (FPM_E_ARG on NaN, Inf or a
+ *              negative value).
+ *   z_out      double [ntiles], host.
+ *   scores_out double [ntiles][scores_per_tile], host, may be NULL: the
+ *              candidates' scores (scores_per_tile >= the candidate count).
+ * Synchronises `hip_stream` before returning.  Errors: FPM_E_ARG (NULL,
+ * z_step <= 0, z_hi < z_lo, iterations outside 1..1000, more than 4096
+ * candidates, scores_out too short), FPM_E_GEOMETRY, FPM_E_DIVERGED (a
+ * score not finite), FPM_E_NOMEM, FPM_E_DEVICE; z_out is untouched then. */
+fpm_status fpm_estimate_defocus(const fpm_tile_desc *tiles, int32_t ntiles,
+                                const float *intensity, fpm_mem where, double z_lo, double z_hi,
+                                double z_step, int32_t iterations, double *z_out,
+                                double *scores_out, int32_t scores_per_tile, void *hip_stream);
 
 /* Stitch reconstructed tiles into one field of view (Sec. 3.1, Eq. (1)).
  *   tiles  complex64 [rows][cols][side][side]: the tile objects on their grid,
@@ -287,7 +321,8 @@ fpm_status fpm_profile_reconstruct(fpm_plan_t *plan, const float *intensity,
 /* ------------------------------------------------------------ serving */
 
 typedef struct {
-  double submit_s;      /* seconds since server start                     */
+  double submit_s;      /* seconds since server start, taken on entry to
+                           fpm_submit                                     */
   double admit_s;       /* admitted (device memory granted)               */
   double finish_s;      /* outputs ready                                  */
   int64_t updates;      /* LED-tile updates the request ran               */
@@ -299,9 +334,13 @@ typedef struct {
  * every admitted request keeps its spectrum and pupil resident; each
  * scheduler tick runs one iteration of every admitted request, step s of all
  * of them in the same launches (continuous batching), and requests join and
- * leave between ticks.  A server that has run a 256-px request also holds
- * 128 MiB of transpose scratch until it is destroyed.
- * Errors: FPM_E_ARG, FPM_E_DEVICE. */
+ * leave between ticks.  The whole budget is allocated as one device slab
+ * when the server is created (FPM_E_NOMEM if it cannot be), and requests
+ * take first-fit pieces of it: the request loop allocates and frees no
+ * device memory, except the tick's work lists for batches beyond 441 LED
+ * updates per slot, and 256 MiB of transpose scratch the first time a
+ * 256-px request runs (held until the server is destroyed).
+ * Errors: FPM_E_ARG, FPM_E_NOMEM, FPM_E_DEVICE. */
 fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_server_t **out);
 void fpm_server_destroy(fpm_server_t *server);
 

@@ -39,6 +39,7 @@ EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_table
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
            "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch",
+           "fpm_estimate_defocus",
            "fpm_online_begin", "fpm_online_push", "fpm_online_finish", "fpm_online_abort")
 
 
@@ -122,6 +123,9 @@ def _load():
     L.fpm_profile_reconstruct.restype = C.c_int
     L.fpm_stitch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int, vp]
     L.fpm_stitch.restype = C.c_int
+    L.fpm_estimate_defocus.argtypes = [C.POINTER(TileDescC), C.c_int32, vp, C.c_int, C.c_double,
+                                       C.c_double, C.c_double, C.c_int32, vp, vp, C.c_int32, vp]
+    L.fpm_estimate_defocus.restype = C.c_int
     L.fpm_online_begin.argtypes = [vp, vp]
     L.fpm_online_begin.restype = C.c_int
     L.fpm_online_push.argtypes = [vp, C.c_int32, vp, C.c_int, vp]
@@ -356,6 +360,28 @@ def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where:
     return check(lib.fpm_stitch(_buf(tiles, where, "c64", count, "tiles"), rows, cols, side,
                                 overlap, _buf(out, where, "c64", H * W, "out"),
                                 where, _stream(stream)))
+
+
+def defocus_candidates(z_lo: float, z_hi: float, z_step: float) -> int:
+    """Number of candidate z values fpm_estimate_defocus scores."""
+    return int(np.floor((z_hi - z_lo) / z_step + 1e-6)) + 1 if z_step > 0 and z_hi >= z_lo else 0
+
+
+def fpm_estimate_defocus(descs, intensity, where: int, z_lo: float = -40.0, z_hi: float = 40.0,
+                         z_step: float = 5.0, iterations: int = 10, stream=None):
+    """Sec. 3.4 Fig. 7b: defocus distance of each tile from its bright-field
+    images (see include/fpm.h).  Returns (z [ntiles], scores [ntiles][K])."""
+    descs = list(descs)
+    arr = (TileDescC * len(descs))(*[to_c_desc(d) for d in descs])
+    count = sum(d.led_rows * d.led_cols * d.n * d.n for d in descs)
+    K = max(defocus_candidates(z_lo, z_hi, z_step), 1)
+    z = np.zeros(len(descs), np.float64)
+    scores = np.zeros((len(descs), K), np.float64)
+    check(lib.fpm_estimate_defocus(arr, len(descs), _buf(intensity, where, "f32", count, "intensity"),
+                                   where, float(z_lo), float(z_hi), float(z_step), int(iterations),
+                                   C.c_void_p(z.ctypes.data), C.c_void_p(scores.ctypes.data), K,
+                                   _stream(stream)))
+    return z, scores
 
 
 def stitched_shape(rows: int, cols: int, side: int, overlap: int):

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpm.so")
-SOURCES = ["kernels.hip", "mfma.hip", "stitch.hip", "plan.cpp", "runtime.cpp", "capi.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "mfma.hip", "stitch.hip", "plan.cpp", "runtime.cpp", "capi.cpp", "serve.cpp",
+           "defocus.cpp"]
 ARCH = os.environ.get("FPM_OFFLOAD_ARCH", "gfx950")
 
 

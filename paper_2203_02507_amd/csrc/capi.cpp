@@ -21,6 +21,11 @@ struct fpm_plan_s {
   int device = -1;
   fpm::Executor exec;
   std::mutex mu;
+  // completion of the last call's device work and the stream it ran on: a
+  // call on another stream waits for it first (calls share the plan's state)
+  hipEvent_t done_ev = nullptr;
+  hipStream_t done_stream = nullptr;
+  bool done_armed = false;
 };
 
 namespace fpm {
@@ -51,6 +56,29 @@ struct DeviceGuard {
 fpm_status ensure_setup(fpm_plan_t* p) {
   if (p->exec.ready) return FPM_OK;
   return p->exec.setup(p->tiles);
+}
+
+// A call's device work goes after the previous call's: device-mode calls
+// return without waiting, and the next one may come on another stream while
+// the first still runs on the plan's state and staging buffers.  A call on
+// the same stream as the previous one is ordered already and waits for
+// nothing (no cross-stream dependency enters a caller's capture).
+fpm_status order_after_previous(fpm_plan_t* p, hipStream_t s) {
+  fpm_status st = FPM_OK;
+  if (p->done_armed && p->done_stream != s &&
+      !hip_ok(hipStreamWaitEvent(s, p->done_ev, 0), "hipStreamWaitEvent(previous call)", &st))
+    return st;
+  return FPM_OK;
+}
+fpm_status mark_done(fpm_plan_t* p, hipStream_t s) {
+  fpm_status st = FPM_OK;
+  if (!p->done_ev &&
+      !hip_ok(hipEventCreateWithFlags(&p->done_ev, hipEventDisableTiming), "hipEventCreate", &st))
+    return st;
+  if (!hip_ok(hipEventRecord(p->done_ev, s), "hipEventRecord(call done)", &st)) return st;
+  p->done_stream = s;
+  p->done_armed = true;
+  return FPM_OK;
 }
 
 // Object (finalised), pupil and residual history of every tile into the
@@ -231,6 +259,7 @@ void fpm_plan_destroy(fpm_plan_t* plan) {
   if (plan->device >= 0) {  // device state exists only once a call has run
     DeviceGuard g(plan);
     (void)hipDeviceSynchronize();
+    if (plan->done_ev) (void)hipEventDestroy(plan->done_ev);
     plan->exec.~Executor();
     new (&plan->exec) Executor();
   }
@@ -333,6 +362,7 @@ fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, 
   if (st != FPM_OK) return st;
   Executor& ex = plan->exec;
   hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   const size_t obj_bytes = sizeof(float2) * ex.total_obj;
   const size_t pup_bytes = sizeof(float2) * ex.total_pupil;
   const size_t int_bytes = sizeof(float) * ex.total_I;
@@ -361,7 +391,7 @@ fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, 
         !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st))
       return st;
   }
-  return FPM_OK;
+  return mark_done(plan, s);
 }
 FPM_ABI_GUARD("fpm_forward")
 
@@ -379,6 +409,7 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   if (st != FPM_OK) return st;
   Executor& ex = plan->exec;
   hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   const size_t int_bytes = sizeof(float) * ex.total_I;
   const float* I = intensity;
   if (where == FPM_MEM_HOST) {
@@ -391,7 +422,9 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
               "set intensity", &st))
     return st;
   if (!hip_ok(ex.run(s, use_graphs()), "reconstruction sweep", &st)) return st;
-  return collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
+  st = collect_outputs(plan, where, object_out, pupil_out, residual_out, s);
+  const fpm_status md = mark_done(plan, s);
+  return st != FPM_OK ? st : md;
 }
 FPM_ABI_GUARD("fpm_reconstruct")
 
@@ -414,6 +447,7 @@ fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) try {
   if (st != FPM_OK) return st;
   Executor& ex = plan->exec;
   hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   if (!ex.tuned) {
     // variant timing scribbles on state that the first push initialises
     if (!hip_ok(ex.tune(s), "update-kernel tuning", &st)) return st;
@@ -426,7 +460,7 @@ fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) try {
     return st;
   ex.online_pushed.assign(L, 0);
   ex.online_count = 0;
-  return FPM_OK;
+  return mark_done(plan, s);
 }
 FPM_ABI_GUARD("fpm_online_begin")
 
@@ -446,6 +480,7 @@ fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_push: cannot select the plan's device");
   hipStream_t s = (hipStream_t)hip_stream;
   fpm_status st = FPM_OK;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   const size_t bytes = sizeof(float) * ex.online_push_floats;
   const float* src = intensity;
   if (where == FPM_MEM_HOST) {
@@ -501,7 +536,7 @@ fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity
       }
     }
   }
-  return FPM_OK;
+  return mark_done(plan, s);
 }
 FPM_ABI_GUARD("fpm_online_push")
 
@@ -519,6 +554,7 @@ fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, 
   if (!g.ok) return fail(FPM_E_DEVICE, "fpm_online_finish: cannot select the plan's device");
   hipStream_t s = (hipStream_t)hip_stream;
   fpm_status st = FPM_OK;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   // iterations 1.. over the whole stack, in the plan's order, chain by chain
   for (size_t p = 0; p < ex.parts.size(); ++p)
     if (ex.part_iter_first[p].size() > 1 &&
@@ -534,6 +570,7 @@ fpm_status fpm_online_finish(fpm_plan_t* plan, fpm_mem where, void* object_out, 
               "restore tile table", &st2) ||
       !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st2))
     return st != FPM_OK ? st : st2;
+  plan->done_armed = false;  // everything has completed
   return st;
 }
 FPM_ABI_GUARD("fpm_online_finish")
@@ -568,12 +605,13 @@ fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
   if (st != FPM_OK) return st;
   Executor& ex = plan->exec;
   hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
   if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, intensity,
                                    (const int64_t*)ex.i_off_d.p, s),
               "set intensity", &st) ||
       !hip_ok(ex.profile(s, out), "profiled sweep", &st))
     return st;
-  return FPM_OK;
+  return mark_done(plan, s);
 }
 FPM_ABI_GUARD("fpm_profile_reconstruct")
 

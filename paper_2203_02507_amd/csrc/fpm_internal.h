@@ -81,10 +81,14 @@ struct StepTile {  // a tile that ran a group in this step
 // transpose buffer and the lines per workgroup: 0..3 Q = 4 with padding 16,
 // 1, 8, 32 complex elements; 4, 5 Q = 8 with padding 1, 16; 6, 7 Q = 8,
 // padding 1, every line of a phase in 2 or 4 rounds of a smaller workgroup
-// (two workgroups per CU).  Every variant computes the same FFTs; the Q = 4
-// and Q = 8 forms differ in the order of their floating-point steps, and the
-// variants of one Q give the same bits.
-constexpr int kUpdateVariants = 8;
+// (two workgroups per CU; their cross-lane steps are fused DPP multiply-adds);
+// 8 Q = 4, padding 1, in 2 rounds.  Every variant computes the same FFTs; the
+// Q = 4 and Q = 8 forms differ in the order of their floating-point steps,
+// and the variants of one Q give the same bits.
+constexpr int kUpdateVariants = 9;
+// the variants the autotuner times: the 8-lane family, whose members give
+// identical bits (the default, variant 7, is one of them)
+constexpr int kTuneFirst = 4, kTuneLast = 7;
 // n = 256 runs a persistent kernel whose workgroups keep their transposes in
 // `big_scratch`: kBigSlots slots of n * n complex values (kBigSlots * 512 KiB);
 // ignored for n <= 128.

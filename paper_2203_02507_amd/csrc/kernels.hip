@@ -18,6 +18,7 @@
 // which the modulus projection and the forward transform cancel exactly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -124,14 +125,18 @@ constexpr int bitrev(int v, int bits) {
   return r;
 }
 
-template <int R, bool INV>
+template <int R, bool INV, int ZLO = 0, int ZHI = 0>
 __device__ __forceinline__ void fft_reg_pow2(float2 (&a)[R]);
 
 // R-point FFT on registers, natural order in and out.  R = 2^k, or 3 * 2^k
 // (one radix-3 decimation-in-time step over three power-of-two sub-FFTs:
 // X[k + M s] = sum_r W_R^{r k} Y_r[k] W_3^{r s}, Y_r the M-point FFT of
 // x[3 m + r]).
-template <int R, bool INV>
+// ZLO / ZHI (power-of-two R only): inputs a[k] with k < ZLO or k >= R - ZHI
+// are known to be zero, and the first butterfly stage skips the arithmetic
+// on them (u + 0 and u - 0 are u, 0 + v and 0 - v are v and -v: the values
+// are those of the full stage up to the sign of an exact zero).
+template <int R, bool INV, int ZLO = 0, int ZHI = 0>
 __device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
   if constexpr (R % 3 == 0) {
     constexpr int M = R / 3;
@@ -160,19 +165,41 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[R]) {
       a[kk + 2 * M] = csub(mid, rot);
     }
   } else {
-    fft_reg_pow2<R, INV>(a);
+    fft_reg_pow2<R, INV, ZLO, ZHI>(a);
   }
 }
 
 // R-point FFT on registers, natural order in and out (R a power of two).
-template <int R, bool INV>
+template <int R, bool INV, int ZLO, int ZHI>
 __device__ __forceinline__ void fft_reg_pow2(float2 (&a)[R]) {
   constexpr int LB = ilog2(R);
   float2 b[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) b[i] = a[bitrev(i, LB)];
+  constexpr int kFirst = ZLO + ZHI > 0 ? 2 : 1;
+  if constexpr (ZLO + ZHI > 0) {
+    // first stage (twiddle 1) with the known-zero inputs folded away
 #pragma unroll
-  for (int half = 1; half < R; half *= 2) {
+    for (int i = 0; i < R; i += 2) {
+      const int iu = bitrev(i, LB), iv = bitrev(i + 1, LB);
+      const bool zu = iu < ZLO || iu >= R - ZHI, zv = iv < ZLO || iv >= R - ZHI;
+      const float2 u = b[i], v = b[i + 1];
+      if (zu && zv) {
+        b[i] = make_float2(0.0f, 0.0f);
+        b[i + 1] = b[i];
+      } else if (zv) {
+        b[i + 1] = u;
+      } else if (zu) {
+        b[i] = v;
+        b[i + 1] = make_float2(-v.x, -v.y);
+      } else {
+        b[i] = cadd(u, v);
+        b[i + 1] = csub(u, v);
+      }
+    }
+  }
+#pragma unroll
+  for (int half = kFirst; half < R; half *= 2) {
 #pragma unroll
     for (int i = 0; i < R; i += 2 * half) {
 #pragma unroll
@@ -360,6 +387,149 @@ __device__ __forceinline__ void xlane16_brev2nat(float2 (&a)[R], int ql, const f
   }
 }
 
+// ------------------------------------ fused cross-lane stages (Q = 8)
+// A cross-lane radix-2 stage as xstage writes it costs two VALU operations
+// per component (a DPP move, then a fused multiply-add).  v_fmac_f32 with a
+// DPP source does both: v <- v + m * partner(v).  It cannot give the lower
+// lane a + b and the upper lane a - b with one multiplier pattern (the op is
+// the same in every lane), but it gives the upper lane b - a = -(a - b): the
+// lane's value comes out negated.  Each lane's values therefore carry a
+// known sign sigma (+-1, the same for all of the lane's values), and a stage
+// with signs sigma_own, sigma_partner and the butterfly sign sgn of
+// xstage uses m = sigma_own * sigma_partner * sgn and yields sigma_own * sgn.
+// Negation commutes with rounding to nearest, so every value is bitwise the
+// xstage value up to its sign.  For the radix-8 steps of line_dit / line_dif:
+// input signs +1 give m = sgn at every stage and output signs
+// par(ql) = (-1)^popcount(ql); input signs par(ql) give m = -sgn and output
+// signs +1.  The callers fold par(ql) into a scalar they multiply by anyway.
+#define FPM_DPP_XOR1 "quad_perm:[1,0,3,2]"
+#define FPM_DPP_XOR2 "quad_perm:[2,3,0,1]"
+#define FPM_DPP_MIRROR8 "row_half_mirror"
+#define FPM_DPP_MIRROR16 "row_mirror"
+// operand i += m * partner(operand i); M is the operand number of m
+#define FPM_FMACD(i, M, C) \
+  "v_fmac_f32_dpp %" #i ", %" #i ", %" #M " " C " row_mask:0xf bank_mask:0xf\n\t"
+// 8 complex values (16 VGPRs) per block.  A DPP source read needs two wait
+// states after a VALU write of that register; the s_nop covers any write the
+// compiler places just before the block, and inside it each instruction
+// reads a register that no earlier instruction of the block wrote.
+#define FPM_FMACD_BLOCK8(C)                                                                   \
+  "s_nop 1\n\t" FPM_FMACD(0, 16, C) FPM_FMACD(1, 16, C) FPM_FMACD(2, 16, C)                     \
+      FPM_FMACD(3, 16, C) FPM_FMACD(4, 16, C) FPM_FMACD(5, 16, C) FPM_FMACD(6, 16, C)           \
+          FPM_FMACD(7, 16, C) FPM_FMACD(8, 16, C) FPM_FMACD(9, 16, C) FPM_FMACD(10, 16, C)      \
+              FPM_FMACD(11, 16, C) FPM_FMACD(12, 16, C) FPM_FMACD(13, 16, C)                    \
+                  FPM_FMACD(14, 16, C) FPM_FMACD(15, 16, C)
+#define FPM_FMACD_BLOCK4(C)                                                                   \
+  "s_nop 1\n\t" FPM_FMACD(0, 8, C) FPM_FMACD(1, 8, C) FPM_FMACD(2, 8, C) FPM_FMACD(3, 8, C)    \
+      FPM_FMACD(4, 8, C) FPM_FMACD(5, 8, C) FPM_FMACD(6, 8, C) FPM_FMACD(7, 8, C)
+
+template <int CTRL>
+__device__ __forceinline__ void fmacd8(float2* a, float m) {
+  if constexpr (CTRL == kXor1)
+    asm volatile(FPM_FMACD_BLOCK8(FPM_DPP_XOR1)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y), "+v"(a[4].x), "+v"(a[4].y),
+                   "+v"(a[5].x), "+v"(a[5].y), "+v"(a[6].x), "+v"(a[6].y), "+v"(a[7].x),
+                   "+v"(a[7].y)
+                 : "v"(m));
+  else if constexpr (CTRL == kXor2)
+    asm volatile(FPM_FMACD_BLOCK8(FPM_DPP_XOR2)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y), "+v"(a[4].x), "+v"(a[4].y),
+                   "+v"(a[5].x), "+v"(a[5].y), "+v"(a[6].x), "+v"(a[6].y), "+v"(a[7].x),
+                   "+v"(a[7].y)
+                 : "v"(m));
+  else if constexpr (CTRL == kMirror8)
+    asm volatile(FPM_FMACD_BLOCK8(FPM_DPP_MIRROR8)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y), "+v"(a[4].x), "+v"(a[4].y),
+                   "+v"(a[5].x), "+v"(a[5].y), "+v"(a[6].x), "+v"(a[6].y), "+v"(a[7].x),
+                   "+v"(a[7].y)
+                 : "v"(m));
+  else
+    asm volatile(FPM_FMACD_BLOCK8(FPM_DPP_MIRROR16)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y), "+v"(a[4].x), "+v"(a[4].y),
+                   "+v"(a[5].x), "+v"(a[5].y), "+v"(a[6].x), "+v"(a[6].y), "+v"(a[7].x),
+                   "+v"(a[7].y)
+                 : "v"(m));
+}
+template <int CTRL>
+__device__ __forceinline__ void fmacd4(float2* a, float m) {
+  if constexpr (CTRL == kXor1)
+    asm volatile(FPM_FMACD_BLOCK4(FPM_DPP_XOR1)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y)
+                 : "v"(m));
+  else if constexpr (CTRL == kXor2)
+    asm volatile(FPM_FMACD_BLOCK4(FPM_DPP_XOR2)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y)
+                 : "v"(m));
+  else if constexpr (CTRL == kMirror8)
+    asm volatile(FPM_FMACD_BLOCK4(FPM_DPP_MIRROR8)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y)
+                 : "v"(m));
+  else
+    asm volatile(FPM_FMACD_BLOCK4(FPM_DPP_MIRROR16)
+                 : "+v"(a[0].x), "+v"(a[0].y), "+v"(a[1].x), "+v"(a[1].y), "+v"(a[2].x),
+                   "+v"(a[2].y), "+v"(a[3].x), "+v"(a[3].y)
+                 : "v"(m));
+}
+#undef FPM_FMACD_BLOCK4
+#undef FPM_FMACD_BLOCK8
+#undef FPM_FMACD
+#undef FPM_DPP_MIRROR16
+#undef FPM_DPP_MIRROR8
+#undef FPM_DPP_XOR2
+#undef FPM_DPP_XOR1
+
+// a[i] <- a[i] + m * partner(a[i]) for all i, both components
+template <int CTRL, int R>
+__device__ __forceinline__ void xstage_fused(float2 (&a)[R], float m) {
+  static_assert(R % 4 == 0, "blocks of 4 complex values");
+#pragma unroll
+  for (int i = 0; i + 8 <= R; i += 8) fmacd8<CTRL>(a + i, m);
+  if constexpr (R % 8 != 0) fmacd4<CTRL>(a + (R / 8) * 8, m);
+}
+
+__device__ __forceinline__ float par8(int ql) {  // (-1)^popcount(ql), ql < 8
+  return (__builtin_popcount(ql) & 1) ? -1.0f : 1.0f;
+}
+
+// xlane8_nat2brev / xlane8_brev2nat with fused stages, stage by stage over
+// the lane's values.  flip = +1: input signs +1, output signs par8(ql);
+// flip = -1: input signs par8(ql), output signs +1.
+template <bool INV, int R>
+__device__ __forceinline__ void xlane8_nat2brev_f(float2 (&a)[R], int ql, float flip) {
+  const float s4 = (ql & 4) ? -flip : flip, s2 = (ql & 2) ? -flip : flip,
+              s1 = (ql & 1) ? -flip : flip;
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+  xstage_fused<kMirror8>(a, s4);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t8);
+  xstage_fused<kXor2>(a, s2);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = w4_lane3<INV>(a[i], is3);
+  xstage_fused<kXor1>(a, s1);
+}
+template <bool INV, int R>
+__device__ __forceinline__ void xlane8_brev2nat_f(float2 (&a)[R], int ql, float flip) {
+  const float s4 = (ql & 4) ? -flip : flip, s2 = (ql & 2) ? -flip : flip,
+              s1 = (ql & 1) ? -flip : flip;
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+  xstage_fused<kXor1>(a, s1);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = w4_lane3<INV>(a[i], is3);
+  xstage_fused<kXor2>(a, s2);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t8);
+  xstage_fused<kMirror8>(a, s4);
+}
+
 // Line FFT over Q lanes, decimation in time.  In: logical lane ql holds
 // x[ql + Q p] in a[p].  Out: it holds X[R * brevq(ql) + k] in a[k].
 template <int n, bool INV, int Q = kQ, int TS = 0>
@@ -386,6 +556,78 @@ __device__ __forceinline__ void line_dif(float2 (&a)[n / Q], int ql, const float
     xlane8_brev2nat<INV>(a, ql);
   else
     xlane16_brev2nat<n, INV, R, TS>(a, ql, tw);
+#pragma unroll
+  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw_at<INV, n, TS>(tw, ql * m));
+  fft_reg<R, INV>(a);
+}
+
+// Q = 16 counterparts (n = 256 kernel): four fused stages; the sign rule is
+// the same with par16(ql) = (-1)^popcount(ql) over four bits.
+__device__ __forceinline__ float par16(int ql) {
+  return (__builtin_popcount(ql) & 1) ? -1.0f : 1.0f;
+}
+template <int n, bool INV, int R, int TS>
+__device__ __forceinline__ void xlane16_nat2brev_f(float2 (&a)[R], int ql, const float2* tw,
+                                                   float flip) {
+  const float s8 = (ql & 8) ? -flip : flip, s4 = (ql & 4) ? -flip : flip,
+              s2 = (ql & 2) ? -flip : flip, s1 = (ql & 1) ? -flip : flip;
+  const float2 t16 = tw_at<INV, n, TS>(tw, (ql & 8) ? (ql & 7) * (n / 16) : 0);
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+  xstage_fused<kMirror16>(a, s8);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t16);
+  xstage_fused<kMirror8>(a, s4);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t8);
+  xstage_fused<kXor2>(a, s2);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = w4_lane3<INV>(a[i], is3);
+  xstage_fused<kXor1>(a, s1);
+}
+template <int n, bool INV, int R, int TS>
+__device__ __forceinline__ void xlane16_brev2nat_f(float2 (&a)[R], int ql, const float2* tw,
+                                                   float flip) {
+  const float s8 = (ql & 8) ? -flip : flip, s4 = (ql & 4) ? -flip : flip,
+              s2 = (ql & 2) ? -flip : flip, s1 = (ql & 1) ? -flip : flip;
+  const float2 t16 = tw_at<INV, n, TS>(tw, (ql & 8) ? (ql & 7) * (n / 16) : 0);
+  const float2 t8 = w8<INV>((ql & 4) ? (ql & 3) : 0);
+  const bool is3 = (ql & 3) == 3;
+  xstage_fused<kXor1>(a, s1);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = w4_lane3<INV>(a[i], is3);
+  xstage_fused<kXor2>(a, s2);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t8);
+  xstage_fused<kMirror8>(a, s4);
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = cmul(a[i], t16);
+  xstage_fused<kMirror16>(a, s8);
+}
+
+// line_dit / line_dif for Q = 8 with the fused cross-lane step (flip as
+// for xlane8_nat2brev_f; the register FFT and twiddles are linear, so the
+// lane signs pass through them unchanged).
+template <int n, bool INV, int TS = 0, int Z = 0, int Q = 8>
+__device__ __forceinline__ void line_dit_f(float2 (&a)[n / Q], int ql, const float2* tw,
+                                           float flip) {
+  constexpr int R = n / Q;
+  fft_reg<R, INV, Z, Z>(a);
+#pragma unroll
+  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw_at<INV, n, TS>(tw, ql * k));
+  if constexpr (Q == 8)
+    xlane8_nat2brev_f<INV>(a, ql, flip);
+  else
+    xlane16_nat2brev_f<n, INV, R, TS>(a, ql, tw, flip);
+}
+template <int n, bool INV, int TS = 0, int Q = 8>
+__device__ __forceinline__ void line_dif_f(float2 (&a)[n / Q], int ql, const float2* tw,
+                                           float flip) {
+  constexpr int R = n / Q;
+  if constexpr (Q == 8)
+    xlane8_brev2nat_f<INV>(a, ql, flip);
+  else
+    xlane16_brev2nat_f<n, INV, R, TS>(a, ql, tw, flip);
 #pragma unroll
   for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw_at<INV, n, TS>(tw, ql * m));
   fft_reg<R, INV>(a);
@@ -459,7 +701,10 @@ __device__ __forceinline__ float wave_max(float v) {
 // Thread (c, q) with c < nd: support column kx = kx0 + c, rows ky = q + 4p.
 // Sw / Pw: buffer views of the LED's spectrum window and of the pupil.
 // Returns the partial max |P|^2 of this thread's support pixels.
-template <int n, int Q = kQ>
+// Z: rows q + Q p with p < Z or p >= R - Z lie outside every chord of the
+// launch (the support's row range starts at or after Q Z and ends at or
+// before n - Q Z), so those values are zero without a load.
+template <int n, int Q = kQ, int Z = 0>
 __device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_buffer_rsrc_t Pw,
                                             int N, int kx, int2 ch, int q, float scale,
                                             float2 (&a)[n / Q]) {
@@ -468,6 +713,10 @@ __device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_
   const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
+    if (p < Z || p >= R - Z) {
+      a[p] = make_float2(0.0f, 0.0f);
+      continue;
+    }
     const int ky = q + Q * p;
     const bool in = ky >= ch.x && ky <= ch.y;
     const float2 xs = bload2(Sw, in ? s0 + p * (Q * 8) * N : kOob);
@@ -479,12 +728,16 @@ __device__ __forceinline__ float gather_phi(__amdgpu_buffer_rsrc_t Sw, __amdgpu_
 }
 
 // phase B input: logical lane q of row y takes kx = q + Q p from T[kx - kx0][y]
-template <int n, int PAD = 16, int Q = kQ>
+template <int n, int PAD = 16, int Q = kQ, int Z = 0>
 __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, int y, int q,
                                           float2 (&a)[n / Q]) {
   constexpr int R = n / Q;
 #pragma unroll
   for (int p = 0; p < R; ++p) {
+    if (p < Z || p >= R - Z) {  // outside every support column (see gather_phi)
+      a[p] = make_float2(0.0f, 0.0f);
+      continue;
+    }
     const int c = q + Q * p - kx0;
     a[p] = (c >= 0 && c < nd) ? buf[c * pitch<n, PAD>() + y] : make_float2(0.0f, 0.0f);
   }
@@ -492,9 +745,11 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
 
 // Modulus projection of one row segment and its residual partials.
 // a[k] holds psi at (row `line`, column xc + k) of the unshifted frame.
+// zpar = 1: the lane's values carry the sign -1 (fused cross-lane steps);
+// the projection is odd in psi, so only the zero-field value needs it.
 template <int R>
 __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[R], int line,
-                                            int xc, float& e_acc, float& i_acc) {
+                                            int xc, float& e_acc, float& i_acc, int zpar = 0) {
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
@@ -505,7 +760,7 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
     // Where psi = 0 the method sets psi' = sqrt(I) in the centred frame; this
     // frame differs from it by (-1)^(x+y), so the zero-field value is
     // (-1)^(x+y) sqrt(I) here.
-    const float m_zero = ((line + xc + k) & 1) ? -m : m;
+    const float m_zero = ((line + xc + k + zpar) & 1) ? -m : m;
     const float p2 = cabs2(a[k]);
     const bool small = p2 < 0x1p-100f;
     const float2 as = small ? cscale(a[k], 0x1p100f) : a[k];
@@ -531,32 +786,34 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 // pupil_reduce_kernel, so both forms give the same bits.
 // The stored spectrum of a support column (the values update_column reads),
 // loaded ahead of the column transform where registers allow.
-template <int n, int Q = kQ>
+template <int n, int Q = kQ, int Z = 0>
 __device__ __forceinline__ void load_column(__amdgpu_buffer_rsrc_t Sw, int N, int kx, int2 ch,
                                             int q, float2 (&xs)[n / Q]) {
   constexpr int R = n / Q;
   const int s0 = (q * N + kx) * 8;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
+    if (k < Z || k >= R - Z) continue;  // outside every chord (see gather_phi)
     const int ky = q + Q * k;
     const bool in = ky >= ch.x && ky <= ch.y;
     xs[k] = bload2(Sw, in ? s0 + k * (Q * 8) * N : kOob);
   }
 }
-template <int n, int Q = kQ>
+template <int n, int Q = kQ, int Z = 0>
 __device__ __forceinline__ void load_pupil_column(__amdgpu_buffer_rsrc_t Pw, int kx, int2 ch,
                                                   int q, float2 (&pv)[n / Q]) {
   constexpr int R = n / Q;
   const int p0 = (q * n + kx) * 8;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
+    if (k < Z || k >= R - Z) continue;  // outside every chord (see gather_phi)
     const int ky = q + Q * k;
     const bool in = ky >= ch.x && ky <= ch.y;
     pv[k] = bload2(Pw, in ? p0 + k * (Q * 8 * n) : kOob);
   }
 }
 
-template <int n, int Q = kQ, bool SEQ = false, bool PRE = false>
+template <int n, int Q = kQ, bool SEQ = false, bool PRE = false, int Z = 0>
 __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Sw,
                                               __amdgpu_buffer_rsrc_t Pw,
@@ -564,14 +821,20 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               int q, float sigf, float pmax2, float smax,
                                               int mode, int slot = 0, int count = 1,
                                               const float2* xs_pre = nullptr,
-                                              const float2* pv_pre = nullptr) {
+                                              const float2* pv_pre = nullptr,
+                                              float lane_sign = 1.0f) {
   constexpr int R = n / Q;
-  const float inv_ps = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
-  const float inv_ss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
+  // a[] may carry a lane sign (fused cross-lane steps): D, and with it both
+  // steps, then come out with that sign, which the step scales cancel; the
+  // products with +-1 are exact, so the bits are those of lane_sign = 1
+  const float inv_ps = lane_sign * (pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f);
+  const float inv_ss = lane_sign * (smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f);
+  const float sig_d = lane_sign * sigf;
   const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
   const bool upd_s = pmax2 > 0.0f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
+    if (k < Z || k >= R - Z) continue;  // outside every chord (see gather_phi)
     const int ky = q + Q * k;
     const bool in = ky >= ch.x && ky <= ch.y;
     const int offS = in ? s0 + k * (Q * 8) * N : kOob;
@@ -582,7 +845,7 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
     // explicit fused multiply-adds: every instantiation of this function
     // rounds the update identically, whatever the compiler contracts elsewhere
     const float2 px = cmul_fma(pv, xs);  // D = Phi' - sigma P X
-    const float2 d = make_float2(fmaf(-px.x, sigf, a[k].x), fmaf(-px.y, sigf, a[k].y));
+    const float2 d = make_float2(fmaf(-px.x, sig_d, a[k].x), fmaf(-px.y, sig_d, a[k].y));
     const float2 ts = cmulc_fma(d, pv);
     bstore2(Sw, upd_s ? offS : kOob,
             make_float2(fmaf(ts.x, inv_ps, xs.x), fmaf(ts.y, inv_ps, xs.y)));
@@ -757,7 +1020,11 @@ __global__ __launch_bounds__(n * Q) void update_kernel(const TileDev* __restrict
 // Each line is transformed exactly as in update_kernel, so both give the
 // same bits.  A phase-B thread reads and writes only its own columns of its
 // own row, so the row transforms work in place without a barrier.
-template <int n, int PAD, int Q, int ROUNDS, bool SEQ>
+// Z (Q = 8 only): the values q + Q k with k < Z or k >= R - Z of every line
+// lie outside the support of every tile of the launch (the launcher derives
+// Z from the widest support), so they are neither loaded nor stored, and
+// the row and column IFFTs skip their first-stage arithmetic.
+template <int n, int PAD, int Q, int ROUNDS, bool SEQ, int Z = 0>
 __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void update_kernel_rounds(
     const TileDev* __restrict__ tiles, const Item* __restrict__ items,
     const int2* __restrict__ ranges, int count) {
@@ -799,10 +1066,17 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
-      const int q = q_item;
+      const int q = R > 16 ? opaque(q_item) : q_item;
       const int kx = t.kx0 + line;
-      pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
-      line_dit<n, true, Q, PT>(a, q, tw);
+      if constexpr (Q == 8) {
+        // input signs par8(q) (folded into the gather scale), output signs +1
+        pm = fmaxf(pm, gather_phi<n, Q, Z>(Sw, Pw, N, kx, t.chord[kx], q,
+                                           par8(q) * (sigf / (float)(n * n)), a));
+        line_dit_f<n, true, PT, Z>(a, q, tw, -1.0f);
+      } else {
+        pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
+        line_dit<n, true, Q, PT>(a, q, tw);
+      }
       float2* dst = sbuf + line * PT + xc;
 #pragma unroll
       for (int k = 0; k < R; ++k) dst[k] = a[k];
@@ -816,22 +1090,32 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
 #pragma unroll 1
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
-    const int q = q_item;
+    const int q = R > 16 ? opaque(q_item) : q_item;
     // the row's intensities are requested first, so that their latency
-    // overlaps the row transform
+    // overlaps the row transform; with 32 points per lane that costs more
+    // registers than the latency it hides, and they are requested after it
     float iv[R];
+    auto load_iv = [&](int row) {
 #pragma unroll
-    for (int v = 0; v < R / 4; ++v) {
-      const v4f f = __builtin_amdgcn_raw_buffer_load_b128(Iw, (line * n + xc + 4 * v) * 4, 0, 0);
-      iv[4 * v] = f.x;
-      iv[4 * v + 1] = f.y;
-      iv[4 * v + 2] = f.z;
-      iv[4 * v + 3] = f.w;
-    }
-    load_rows<n, PAD, Q>(sbuf, t.kx0, t.nd, line, q, a);
-    line_dit<n, true, Q, PT>(a, q, tw);
+      for (int v = 0; v < R / 4; ++v) {
+        const v4f f = __builtin_amdgcn_raw_buffer_load_b128(Iw, (row * n + xc + 4 * v) * 4, 0, 0);
+        iv[4 * v] = f.x;
+        iv[4 * v + 1] = f.y;
+        iv[4 * v + 2] = f.z;
+        iv[4 * v + 3] = f.w;
+      }
+    };
+    if constexpr (R <= 16) load_iv(line);
+    load_rows<n, PAD, Q, Z>(sbuf, t.kx0, t.nd, line, q, a);
+    // Q = 8: the row IFFT leaves lane signs par8(q), which the modulus keeps
+    // and the row FFT removes
+    if constexpr (Q == 8)
+      line_dit_f<n, true, PT, Z>(a, q, tw, 1.0f);
+    else
+      line_dit<n, true, Q, PT>(a, q, tw);
+    if constexpr (R > 16) load_iv(opaque(line));
     float e_acc = 0.0f, i_acc = 0.0f;
-    modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
+    modulus_row<R>(a, iv, line, xc, e_acc, i_acc, Q == 8 ? (__builtin_popcount(q) & 1) : 0);
     {
       const double e = wave_sum((double)e_acc), s2 = wave_sum((double)i_acc);
       if ((tid & 63) == 0) {
@@ -839,9 +1123,13 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         red_i[rd * NW + wave] = s2;
       }
     }
-    line_dif<n, false, Q, PT>(a, q, tw);
+    if constexpr (Q == 8)
+      line_dif_f<n, false, PT>(a, q, tw, -1.0f);
+    else
+      line_dif<n, false, Q, PT>(a, q, tw);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
+      if (k < Z || k >= R - Z) continue;  // no support column there
       const int c = q + Q * k - t.kx0;
       if (c >= 0 && c < t.nd) sbuf[c * PT + line] = a[k];
     }
@@ -857,19 +1145,30 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
-      const int q = q_item;
+      const int q = R > 16 ? opaque(q_item) : q_item;
       const int kx = t.kx0 + line;
       const int2 ch = t.chord[kx];
-      // the column's stored spectrum is requested before its transform
-      float2 xs[R], pv[R];
-      load_column<n, Q>(Sw, N, kx, ch, q, xs);
-      load_pupil_column<n, Q>(Pw, kx, ch, q, pv);
+      // the column's stored spectrum is requested before its transform where
+      // registers allow (R <= 16); longer lane segments load it in the update
+      constexpr bool kPre = R <= 16;
+      float2 xs[kPre ? R : 1], pv[kPre ? R : 1];
+      if constexpr (kPre) {
+        load_column<n, Q, Z>(Sw, N, kx, ch, q, xs);
+        load_pupil_column<n, Q, Z>(Pw, kx, ch, q, pv);
+      }
       const float2* srcp = sbuf + line * PT + xc;
 #pragma unroll
       for (int m = 0; m < R; ++m) a[m] = srcp[m];
-      line_dif<n, false, Q, PT>(a, q, tw);
-      update_column<n, Q, SEQ, true>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
-                                     it.slot, it.gsize, xs, pv);
+      if constexpr (Q == 8) {
+        // output signs par8(q), cancelled inside the update
+        line_dif_f<n, false, PT>(a, q, tw, 1.0f);
+        update_column<n, Q, SEQ, kPre, Z>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
+                                          it.slot, it.gsize, xs, pv, par8(q));
+      } else {
+        line_dif<n, false, Q, PT>(a, q, tw);
+        update_column<n, Q, SEQ, kPre>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
+                                       it.slot, it.gsize, xs, pv);
+      }
     }
   }
   if (tid == 0) {
@@ -948,7 +1247,9 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 // so no other thread's input is overwritten.
 constexpr int kBigThreads = 512;
 
-template <int n, int Q>
+// FUSED (Q = 16): the fused cross-lane steps and the support pruning Z of
+// update_kernel_rounds, with the same lane-sign bookkeeping (par16).
+template <int n, int Q, bool FUSED = false, int Z = 0>
 __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
                                                                  const Item* __restrict__ items,
                                                                  int count,
@@ -1001,8 +1302,14 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       asm volatile("" : "+v"(q));
       if (line < t.nd) {
         const int kx = t.kx0 + line;
-        pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
-        line_dit<n, true, Q>(a, q, tw);
+        if constexpr (FUSED) {
+          pm = fmaxf(pm, gather_phi<n, Q, Z>(Sw, Pw, N, kx, t.chord[kx], q,
+                                             par16(q) * (sigf / (float)(n * n)), a));
+          line_dit_f<n, true, 0, Z, Q>(a, q, tw, -1.0f);
+        } else {
+          pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
+          line_dit<n, true, Q>(a, q, tw);
+        }
         float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
 #pragma unroll
         for (int k = 0; k < R / 2; ++k)
@@ -1020,8 +1327,11 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       const int line = l0 + LPR * rd;
       int q = q_item;  // opaque per round: keeps twiddle reads inside the round
       asm volatile("" : "+v"(q));
-      load_rows<n, 0, Q>(sb, t.kx0, t.nd, line, q, a);
-      line_dit<n, true, Q>(a, q, tw);
+      load_rows<n, 0, Q, Z>(sb, t.kx0, t.nd, line, q, a);
+      if constexpr (FUSED)
+        line_dit_f<n, true, 0, Z, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
+      else
+        line_dit<n, true, Q>(a, q, tw);
       float iv[R];
 #pragma unroll
       for (int v = 0; v < R / 4; ++v) {
@@ -1031,10 +1341,16 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
         iv[4 * v + 2] = f.z;
         iv[4 * v + 3] = f.w;
       }
-      modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
-      line_dif<n, false, Q>(a, q, tw);
+      if constexpr (FUSED) {
+        modulus_row<R>(a, iv, line, xc, e_acc, i_acc, __builtin_popcount(q) & 1);
+        line_dif_f<n, false, 0, Q>(a, q, tw, -1.0f);  // lane signs removed
+      } else {
+        modulus_row<R>(a, iv, line, xc, e_acc, i_acc);
+        line_dif<n, false, Q>(a, q, tw);
+      }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
+        if (k < Z || k >= R - Z) continue;  // no support column there
         const int c = q + Q * k - t.kx0;
         if (c >= 0 && c < t.nd) sb[(size_t)c * n + line] = a[k];
       }
@@ -1066,9 +1382,15 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           a[2 * k] = make_float2(f.x, f.y);
           a[2 * k + 1] = make_float2(f.z, f.w);
         }
-        line_dif<n, false, Q>(a, q, tw);
         const int kx = t.kx0 + line;
-        update_column<n, Q>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
+        if constexpr (FUSED) {
+          line_dif_f<n, false, 0, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
+          update_column<n, Q, false, false, Z>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2,
+                                               smax, t.mode, 0, 1, nullptr, nullptr, par16(q));
+        } else {
+          line_dif<n, false, Q>(a, q, tw);
+          update_column<n, Q>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
+        }
       }
     }
     if (tid == 0) {
@@ -1449,19 +1771,51 @@ hipError_t launch_update_np(const TileDev* tiles, const Item* items, int count, 
   }
   return hipGetLastError();
 }
+template <int n, int PAD, int Q, int ROUNDS, int Z>
+hipError_t launch_update_rounds_z(const TileDev* tiles, const Item* items, int count, size_t lds,
+                                  const int2* ranges, int nranges, hipStream_t st) {
+  if (ranges) {
+    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, true, Z>), dim3(nranges),
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, ranges, nranges);
+  } else {
+    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, false, Z>), dim3(xcd_grid(count)),
+                       dim3(n * Q / ROUNDS), lds, st, tiles, items, nullptr, count);
+  }
+  return hipGetLastError();
+}
+// Values a lane may skip at each end of a line (kernel template Z): the
+// support D0 is the disc centred at n/2, so every tile of the launch has its
+// support columns and rows within n/2 - R .. n/2 + R, R = nd_max / 2 (at
+// least half the widest support), and Z Q <= n/2 - R - 1 keeps both ends clear.
+template <int n, int Q>
+constexpr int prune_limit() {
+  return Q == 8 ? (n / Q >= 16 ? 3 : (n / Q >= 12 ? 2 : 1)) : 0;
+}
+inline int prune_count(int n, int Q, int nd_max) {
+  const int lim = n / 2 - nd_max / 2 - 1;
+  return lim > 0 ? lim / Q : 0;
+}
 template <int n, int PAD, int Q, int ROUNDS>
 hipError_t launch_update_rounds(const TileDev* tiles, const Item* items, int count, int nd_max,
                                 const int2* ranges, int nranges, hipStream_t st) {
   // rows: the support columns, and at least n/2 for the twiddle column
   const size_t lds = update_lds<n, PAD>(nd_max > n / 2 ? nd_max : n / 2);
-  if (ranges) {
-    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, true>), dim3(nranges),
-                       dim3(n * Q / ROUNDS), lds, st, tiles, items, ranges, nranges);
-  } else {
-    hipLaunchKernelGGL((update_kernel_rounds<n, PAD, Q, ROUNDS, false>), dim3(xcd_grid(count)),
-                       dim3(n * Q / ROUNDS), lds, st, tiles, items, nullptr, count);
-  }
-  return hipGetLastError();
+  constexpr int zl = prune_limit<n, Q>();
+  const int z = Q == 8 ? std::min(zl, prune_count(n, Q, nd_max)) : 0;
+  if constexpr (zl >= 3)
+    if (z >= 3)
+      return launch_update_rounds_z<n, PAD, Q, ROUNDS, 3>(tiles, items, count, lds, ranges,
+                                                         nranges, st);
+  if constexpr (zl >= 2)
+    if (z >= 2)
+      return launch_update_rounds_z<n, PAD, Q, ROUNDS, 2>(tiles, items, count, lds, ranges,
+                                                         nranges, st);
+  if constexpr (zl >= 1)
+    if (z >= 1)
+      return launch_update_rounds_z<n, PAD, Q, ROUNDS, 1>(tiles, items, count, lds, ranges,
+                                                         nranges, st);
+  return launch_update_rounds_z<n, PAD, Q, ROUNDS, 0>(tiles, items, count, lds, ranges, nranges,
+                                                     st);
 }
 template <int n>
 hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, int nd_max,
@@ -1477,6 +1831,8 @@ hipError_t launch_update_n(const TileDev* tiles, const Item* items, int count, i
       return launch_update_rounds<n, 1, 8, 2>(tiles, items, count, nd_max, ranges, nranges, st);
     case 7:
       return launch_update_rounds<n, 1, 8, 4>(tiles, items, count, nd_max, ranges, nranges, st);
+    case 8:
+      return launch_update_rounds<n, 1, 4, 2>(tiles, items, count, nd_max, ranges, nranges, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1487,6 +1843,15 @@ hipError_t launch_forward_n(const TileDev* tiles, const Item* items, int count, 
   hipLaunchKernelGGL(forward_kernel<n>, dim3(count), dim3(n * kQ), lds, st, tiles, items, out,
                      off);
   return hipGetLastError();
+}
+// the LDS limit of every round-form instantiation Z = 0 .. ZMAX
+template <int n, int Q, int ROUNDS, int ZMAX>
+void set_rounds_attr(int big) {
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, Q, ROUNDS, false, ZMAX>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, Q, ROUNDS, true, ZMAX>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if constexpr (ZMAX > 0) set_rounds_attr<n, Q, ROUNDS, ZMAX - 1>(big);
 }
 template <int n>
 void set_lds_limit_n(int big) {
@@ -1514,14 +1879,9 @@ void set_lds_limit_n(int big) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)update_kernel<n, 16, 8, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 2, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 2, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 4, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)update_kernel_rounds<n, 1, 8, 4, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  set_rounds_attr<n, 8, 2, prune_limit<n, 8>()>(big);
+  set_rounds_attr<n, 8, 4, prune_limit<n, 8>()>(big);
+  set_rounds_attr<n, 4, 2, 0>(big);
   (void)hipFuncSetAttribute((const void*)forward_kernel<n>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
@@ -1547,12 +1907,30 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
     // 16 lanes per line (R = 16: no spills); variant 1: 8 lanes (R = 32)
     const int grid = xcd_grid(count) < kBigSlots ? xcd_grid(count) : kBigSlots;
     static_assert(kBigSlots % kXcds == 0, "whole XCD blocks of slots");
-    if (variant == 1)
+    // variant 1: 8 lanes per line (R = 32); 3: 16 lanes with the fused
+    // cross-lane steps and support pruning (the same bits as the default up
+    // to the sign of exact zeros); otherwise 16 lanes, unfused
+    if (variant == 1) {
       hipLaunchKernelGGL((update_kernel_big<256, 8>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);
-    else
+    } else if (variant != 3) {
       hipLaunchKernelGGL((update_kernel_big<256, 16>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);
+    } else {
+      const int z = std::min(3, prune_count(256, 16, nd_max));
+      if (z >= 3)
+        hipLaunchKernelGGL((update_kernel_big<256, 16, true, 3>), dim3(grid), dim3(kBigThreads), 0,
+                           st, tiles, items, count, big_scratch);
+      else if (z == 2)
+        hipLaunchKernelGGL((update_kernel_big<256, 16, true, 2>), dim3(grid), dim3(kBigThreads), 0,
+                           st, tiles, items, count, big_scratch);
+      else if (z == 1)
+        hipLaunchKernelGGL((update_kernel_big<256, 16, true, 1>), dim3(grid), dim3(kBigThreads), 0,
+                           st, tiles, items, count, big_scratch);
+      else
+        hipLaunchKernelGGL((update_kernel_big<256, 16, true, 0>), dim3(grid), dim3(kBigThreads), 0,
+                           st, tiles, items, count, big_scratch);
+    }
     return hipGetLastError();
   }
   switch (n) {

@@ -754,7 +754,11 @@ hipError_t Executor::tune(hipStream_t s) {
     const Launch& l = *kv.second;
     int best = 0;
     float best_ms = 1e30f;
-    for (int v = 0; v < kUpdateVariants && e == hipSuccess; ++v) {
+    // only the 8-lane family (variants 4-7): its variants differ in layout
+    // alone and give the same bits, so a reconstruction's result does not
+    // depend on which of them the timing picks (the 4-lane family rounds
+    // differently and is selectable through FPM_UPDATE_VARIANT only)
+    for (int v = kTuneFirst; v <= kTuneLast && e == hipSuccess; ++v) {
       const int2* rg = l.roff >= 0 ? (const int2*)ranges_d.p + l.roff : nullptr;
       e = launch_update(l.n, tab, it + l.off, l.count, l.nd_max, v, nullptr, s, rg,
                         l.rcount);  // warm-up

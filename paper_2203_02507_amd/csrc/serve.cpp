@@ -10,6 +10,15 @@
 // admitted and retired between ticks.  Each request's arithmetic is independent of
 // what it is batched with (one workgroup per update, per-tile reductions in
 // fixed order), so a result is bitwise the same alone and in a mix.
+//
+// Device memory: the whole budget is one slab allocated when the server is
+// created; requests take first-fit pieces of it and give them back, so the
+// request loop itself never calls hipMalloc or hipFree (the tick's work
+// lists are sized at creation too and grow only for unusually large
+// batches).  The worker holds the server's mutex only to move requests
+// between queues and to publish results: the device work of an admission
+// (uploads, initial state) and of a retirement (object, copies back) runs
+// outside it, so callers submitting or polling are never held up by it.
 #include <algorithm>
 #include <cstdlib>
 #include <chrono>
@@ -48,6 +57,8 @@ struct Request {
   size_t dev_bytes = 0;
   TileDev td{};
   int slot = -1;
+  int slot_id = -1;  // host source of the admission's slot-id upload
+  LineJob jobs_host[4] = {};  // host source of the admission's line-job upload
   float2* obj_stage = nullptr;
   float* I_copy = nullptr;
   // progress
@@ -80,10 +91,67 @@ size_t footprint(const TilePlan& tp, fpm_mem where) {
   return b;
 }
 
+// First-fit allocator over one device slab.  Pieces are 256-byte aligned;
+// free pieces are kept by offset and merged with their neighbours when given
+// back.  Host bookkeeping only: giving a piece back does not wait for the
+// device, so the caller gives back only memory no queued work still uses.
+struct Slab {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  hipError_t init(size_t bytes) {
+    size = align256(bytes);
+    hipError_t e = hipMalloc(&base, size);
+    if (e != hipSuccess) {
+      base = nullptr;
+      return e;
+    }
+    free_[0] = size;
+    return hipSuccess;
+  }
+  ~Slab() {
+    if (base) (void)hipFree(base);
+  }
+  void* take(size_t bytes) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, rest = it->second - bytes;
+      free_.erase(it);
+      if (rest) free_[off + bytes] = rest;
+      used += bytes;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void give(void* p, size_t bytes) {
+    bytes = align256(bytes);
+    size_t off = (size_t)((char*)p - base);
+    used -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+};
+
 }  // namespace
 
+// LED updates per slot the tick's work lists are sized for at creation
+constexpr size_t kListLedsPerSlot = 441;
+
 struct fpm_server_s {
-  size_t budget = 0, used = 0;
+  size_t budget = 0;
+  Slab slab;  // the whole budget, allocated at creation
   int max_slots = 0;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -109,30 +177,42 @@ struct fpm_server_s {
   DevBuf big_scratch;
   std::vector<int> free_slots;
   std::vector<TileDev> host_table;
+  const int64_t zero_off = 0;  // host source of the retirement's offset upload
   fpm_status fatal = FPM_OK;
 
   void run();
-  bool admit(Request* r, std::string& err);
+  bool reserve(Request* r);
+  hipError_t admit(Request* r);
   void release(Request* r);
   hipError_t tick(std::vector<Request*>& batch);
   hipError_t tick_part(std::vector<Request*>& batch, int part);
   hipError_t finish(Request* r);
 };
 
-bool fpm_server_s::admit(Request* r, std::string& err) {
+// Under the server's mutex: a piece of the slab and a table slot for r, or
+// false (nothing taken) when either is missing.
+bool fpm_server_s::reserve(Request* r) {
+  if (free_slots.empty()) return false;
+  const size_t bytes = footprint(r->plan, r->where);
+  void* p = slab.take(bytes);
+  if (!p) return false;
+  r->dev = p;
+  r->dev_bytes = bytes;
+  r->slot = free_slots.back();
+  free_slots.pop_back();
+  return true;
+}
+
+// Outside the mutex: the request's device state in its reserved piece and
+// slot, and its initial state, enqueued on the first stream (the caller
+// synchronises once for all requests admitted together).
+hipError_t fpm_server_s::admit(Request* r) {
   const TilePlan& tp = r->plan;
   const size_t nn = (size_t)tp.n * tp.n, NN = (size_t)tp.N * tp.N;
-  r->dev_bytes = footprint(tp, r->where);
   if (tp.d.precision != FPM_PREC_FP32_FFT) {
     const uint16_t *E = nullptr, *F = nullptr;  // built once per process and size
-    if (dft_tables(tp.n, tp.d.precision, &E, &F) != hipSuccess) {
-      err = "DFT tables";
-      return false;
-    }
-  }
-  if (hipMalloc(&r->dev, r->dev_bytes) != hipSuccess) {
-    err = "hipMalloc failed";
-    return false;
+    const hipError_t e = dft_tables(tp.n, tp.d.precision, &E, &F);
+    if (e != hipSuccess) return e;
   }
   char* p = (char*)r->dev;
   auto take = [&](size_t bytes) {
@@ -177,8 +257,9 @@ bool fpm_server_s::admit(Request* r, std::string& err) {
                        stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync((void*)d.P0, tp.pupil0.data(), nn * 8, hipMemcpyHostToDevice, stream);
-  // line-FFT jobs: initial window rows/cols (forward), object rows/cols (inverse)
-  LineJob hj[4];
+  // line-FFT jobs: initial window rows/cols (forward), object rows/cols
+  // (inverse); the host copy lives in the request until the upload has run
+  LineJob* hj = r->jobs_host;
   for (int pass = 0; pass < 2; ++pass) {
     LineJob& j = hj[pass];
     j = LineJob{};
@@ -197,37 +278,31 @@ bool fpm_server_s::admit(Request* r, std::string& err) {
     f.modulate = pass == 1;
   }
   if (e == hipSuccess)
-    e = hipMemcpyAsync(jobs_dev, hj, sizeof hj, hipMemcpyHostToDevice, stream);
-  // table slot
-  r->slot = free_slots.back();
-  free_slots.pop_back();
+    e = hipMemcpyAsync(jobs_dev, hj, sizeof r->jobs_host, hipMemcpyHostToDevice, stream);
+  // the table slot (reserved under the mutex; only the worker writes slots)
   host_table[r->slot] = d;
   TileDev* tab = (TileDev*)table.p;
   if (e == hipSuccess)
     e = hipMemcpyAsync(tab + r->slot, &host_table[r->slot], sizeof(TileDev), hipMemcpyHostToDevice,
                        stream);
-  // initial state
-  int* ids_d = (int*)ids.p;
+  // initial state; the slot id is read from the table entry's own copy, which
+  // stays put until the caller's synchronisation
+  r->slot_id = r->slot;
+  int* ids_d = (int*)r->td.residual;  // scratch until the first iteration ends
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ids_d, &r->slot, sizeof(int), hipMemcpyHostToDevice, stream);
+    e = hipMemcpyAsync(ids_d, &r->slot_id, sizeof(int), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = launch_init_state(tab, ids_d, 1, d.n, d.N, stream);
   if (e == hipSuccess) e = launch_line_fft(jobs_dev, 1, d.n, d.n, 0, stream);
   if (e == hipSuccess) e = launch_line_fft(jobs_dev + 1, 1, d.n, d.n, 0, stream);
   if (e == hipSuccess) e = launch_smax(tab, ids_d, 1, d.N * d.N, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  r->stats.admit_s = now_s(t0);
-  used += r->dev_bytes;
-  if (e != hipSuccess) {
-    err = std::string("admission: ") + hipGetErrorString(e);
-    return false;
-  }
-  return true;
+  return e;
 }
 
+// Under the mutex, with no queued work left on r's memory: its piece of the
+// slab and its slot go back.
 void fpm_server_s::release(Request* r) {
   if (r->dev) {
-    (void)hipFree(r->dev);
-    used -= r->dev_bytes;
+    slab.give(r->dev, r->dev_bytes);
     r->dev = nullptr;
   }
   if (r->slot >= 0) {
@@ -236,6 +311,9 @@ void fpm_server_s::release(Request* r) {
   }
 }
 
+// Outside the mutex: the request's object, pupil and residuals, enqueued on
+// the first stream into its host vectors (the caller synchronises once for
+// all requests retired together).
 hipError_t fpm_server_s::finish(Request* r) {
   // object = up^2 IFFT_N(shift(sigma S)): scale into the stage, two passes of line IFFTs
   const TilePlan& tp = r->plan;
@@ -245,8 +323,7 @@ hipError_t fpm_server_s::finish(Request* r) {
                                              (r->where == FPM_MEM_HOST
                                                   ? align256((size_t)tp.L * nn * 4)
                                                   : 0));
-  int64_t zero = 0;
-  hipError_t e = hipMemcpyAsync(ids.p, &zero, sizeof zero, hipMemcpyHostToDevice, stream);
+  hipError_t e = hipMemcpyAsync(ids.p, &zero_off, sizeof zero_off, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = launch_scale_spectrum(tab + r->slot, 1, r->obj_stage, (const int64_t*)ids.p, tp.N, stream);
   if (e == hipSuccess) e = launch_line_fft(jobs_dev + 2, 1, tp.N, tp.N, 1, stream);
@@ -261,7 +338,6 @@ hipError_t fpm_server_s::finish(Request* r) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(r->residual.data(), r->td.residual, r->residual.size() * 8,
                        hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   return e;
 }
 
@@ -419,12 +495,12 @@ hipError_t fpm_server_s::tick_part(std::vector<Request*>& batch, int part) {
 void fpm_server_s::run() {
   (void)hipSetDevice(device);
   while (true) {
-    std::vector<Request*> batch;
+    std::vector<Request*> batch, admitting, retiring;
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !waiting.empty() || !active.empty(); });
       if (stop) break;
-      // drop cancelled requests
+      // drop cancelled requests (no work of theirs is queued between ticks)
       for (auto it = active.begin(); it != active.end();) {
         if ((*it)->cancelled) {
           release(*it);
@@ -436,8 +512,10 @@ void fpm_server_s::run() {
           ++it;
         }
       }
-      // admission by device footprint and free slots (first come, first served)
-      while (!waiting.empty() && (int)active.size() < max_slots) {
+      // admission by device footprint and free slots (first come, first
+      // served): a piece of the slab and a slot are reserved here, the
+      // device work runs below without the mutex
+      while (!waiting.empty()) {
         Request* r = waiting.front();
         if (r->cancelled) {
           waiting.pop_front();
@@ -446,54 +524,77 @@ void fpm_server_s::run() {
           cv_done.notify_all();
           continue;
         }
-        if (used + footprint(r->plan, r->where) > budget) break;
+        if (!reserve(r)) break;
         waiting.pop_front();
-        std::string err;
-        if (!admit(r, err)) {
-          release(r);
-          r->status = FPM_E_DEVICE;
-          r->err = "admission: " + err;
-          cv_done.notify_all();
-          continue;
-        }
-        if (r->plan.d.iterations == 0) {
-          const hipError_t e = finish(r);
-          release(r);
-          r->status = e == hipSuccess ? FPM_OK : FPM_E_DEVICE;
-          if (e != hipSuccess) r->err = std::string("result copy: ") + hipGetErrorString(e);
-          r->stats.finish_s = now_s(t0);
-          cv_done.notify_all();
-          continue;
-        }
-        active.push_back(r);
+        admitting.push_back(r);
       }
       batch = active;
     }
-    if (batch.empty()) continue;
-    hipError_t e;
-    try {
-      e = tick(batch);
-    } catch (const std::exception&) {  // host allocation of the tick's work lists
-      e = hipErrorOutOfMemory;
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    if (e != hipSuccess) {
-      for (Request* r : batch) {
-        release(r);
-        r->status = FPM_E_DEVICE;
-        r->err = std::string("server tick: ") + hipGetErrorString(e);
+    // admissions: every new request's initial state, one synchronisation
+    if (!admitting.empty()) {
+      std::vector<hipError_t> err(admitting.size(), hipSuccess);
+      for (size_t k = 0; k < admitting.size(); ++k) err[k] = admit(admitting[k]);
+      const hipError_t se = hipStreamSynchronize(stream);
+      const double t_adm = now_s(t0);
+      std::lock_guard<std::mutex> lk(mu);
+      for (size_t k = 0; k < admitting.size(); ++k) {
+        Request* r = admitting[k];
+        const hipError_t e = err[k] != hipSuccess ? err[k] : se;
+        r->stats.admit_s = t_adm;
+        if (e != hipSuccess) {
+          release(r);
+          r->status = FPM_E_DEVICE;
+          r->err = std::string("admission: ") + hipGetErrorString(e);
+          cv_done.notify_all();
+        } else if (r->plan.d.iterations == 0) {
+          retiring.push_back(r);
+        } else {
+          active.push_back(r);
+          batch.push_back(r);
+        }
       }
-      active.clear();
-      fatal = FPM_E_DEVICE;
-      cv_done.notify_all();
-      continue;
     }
-    for (auto it = active.begin(); it != active.end();) {
-      Request* r = *it;
-      r->stats.updates += r->plan.L;  // a tick runs one whole iteration
-      const bool done = ++r->iter == r->plan.d.iterations;
-      if (done) {
-        const hipError_t fe = finish(r);
+    if (!batch.empty()) {
+      hipError_t e;
+      try {
+        e = tick(batch);
+      } catch (const std::exception&) {  // host allocation of the tick's work lists
+        e = hipErrorOutOfMemory;
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      if (e != hipSuccess) {
+        for (Request* r : batch) {
+          release(r);
+          r->status = FPM_E_DEVICE;
+          r->err = std::string("server tick: ") + hipGetErrorString(e);
+        }
+        active.clear();
+        fatal = FPM_E_DEVICE;
+        cv_done.notify_all();
+        continue;
+      }
+      for (auto it = active.begin(); it != active.end();) {
+        Request* r = *it;
+        r->stats.updates += r->plan.L;  // a tick runs one whole iteration
+        if (++r->iter == r->plan.d.iterations) {
+          retiring.push_back(r);
+          it = active.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    // retirements: objects and copies back for every finished request, one
+    // synchronisation, then the results are published
+    if (!retiring.empty()) {
+      std::vector<hipError_t> err(retiring.size(), hipSuccess);
+      for (size_t k = 0; k < retiring.size(); ++k) err[k] = finish(retiring[k]);
+      const hipError_t se = hipStreamSynchronize(stream);
+      const double t_fin = now_s(t0);
+      std::lock_guard<std::mutex> lk(mu);
+      for (size_t k = 0; k < retiring.size(); ++k) {
+        Request* r = retiring[k];
+        const hipError_t fe = err[k] != hipSuccess ? err[k] : se;
         bool finite = true;
         for (double v : r->residual) finite &= std::isfinite(v);
         release(r);
@@ -502,12 +603,9 @@ void fpm_server_s::run() {
           r->err = std::string("result copy: ") + hipGetErrorString(fe);
         else if (!finite)
           r->err = "residual became non-finite";
-        r->stats.finish_s = now_s(t0);
-        it = active.erase(it);
-        cv_done.notify_all();
-      } else {
-        ++it;
+        r->stats.finish_s = t_fin;
       }
+      cv_done.notify_all();
     }
   }
 }
@@ -536,7 +634,17 @@ fpm_status fpm_server_create(size_t hbm_budget_bytes, int32_t max_slots, fpm_ser
               &st) ||
       !hip_ok(s->table.alloc(sizeof(TileDev) * max_slots), "hipMalloc(table)", &st) ||
       !hip_ok(s->ids.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st) ||
-      !hip_ok(s->ids2.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st))
+      !hip_ok(s->ids2.alloc(sizeof(int64_t) * std::max(2, max_slots)), "hipMalloc(ids)", &st) ||
+      // work lists of a tick, sized for every slot holding a 21 x 21 board
+      !hip_ok(s->items.alloc(sizeof(Item) * kListLedsPerSlot * max_slots), "hipMalloc(items)",
+              &st) ||
+      !hip_ok(s->items2.alloc(sizeof(Item) * kListLedsPerSlot * max_slots), "hipMalloc(items)",
+              &st) ||
+      !hip_ok(s->steps.alloc(sizeof(StepTile) * kListLedsPerSlot * max_slots),
+              "hipMalloc(steps)", &st) ||
+      !hip_ok(s->steps2.alloc(sizeof(StepTile) * kListLedsPerSlot * max_slots),
+              "hipMalloc(steps)", &st) ||
+      !hip_ok(s->slab.init(hbm_budget_bytes), "hipMalloc(server slab)", &st))
     return undo(st);
   try {
     s->host_table.assign(max_slots, TileDev{});
@@ -572,6 +680,8 @@ fpm_status fpm_submit(fpm_server_t* s, const fpm_tile_desc* tile, const float* i
                       fpm_mem where, uint64_t* id) try {
   if (!s || !tile || !intensity || !id || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))
     return fail(FPM_E_ARG, "fpm_submit: bad argument");
+  // the request's latency clock starts when the call is made
+  const double t_arrive = now_s(s->t0);
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return fail(FPM_E_NOMEM, "fpm_submit: host allocation failed");
   std::string err;
@@ -591,7 +701,7 @@ fpm_status fpm_submit(fpm_server_t* s, const fpm_tile_desc* tile, const float* i
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->fatal != FPM_OK) return fail(s->fatal, "fpm_submit: server stopped after a device error");
   r->id = s->next_id++;
-  r->stats.submit_s = now_s(s->t0);
+  r->stats.submit_s = t_arrive;
   r->stats.status = FPM_PENDING;
   *id = r->id;
   s->waiting.push_back(r.get());

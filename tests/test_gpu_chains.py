@@ -81,5 +81,5 @@ def test_results_do_not_depend_on_chains_or_graph(fpm, orc, monkeypatch):
         err = rel(ref[t][0], o_ref)
         print(f"tile {t} n {d.n} schedule {d.schedule} precision {d.precision}: rel L2 {err:.3e}")
         assert err <= (1e-4 if d.precision == 0 else 1e-3), t
-        check_windows(orc, d, ref[t][0], o_ref,
+        check_windows(orc, d, Is[t], ref[t][0], o_ref,
                       1e-3 if d.precision == 0 else TOL_WIN_MFMA[d.precision], f"tile {t}")

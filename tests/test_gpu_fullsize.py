@@ -86,7 +86,7 @@ def test_full_field_sampled_tiles_match_oracle(fpm, orc):
         err, perr = rel(o, o_ref), rel(P, P_ref)
         print(f"tile {t}: rel L2 object {err:.3e} pupil {perr:.3e}", flush=True)
         assert err <= TOL and perr <= TOL, t
-        check_windows(orc, descs[t], o, o_ref, TOL_WIN, f"tile {t}")
+        check_windows(orc, descs[t], stacks[t], o, o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
     # the sampled tiles alone: the same bits as in the full batch
@@ -101,5 +101,5 @@ def test_full_field_sampled_tiles_match_oracle(fpm, orc):
             err, perr = rel(mout[t][0], o_ref), rel(mout[t][1], P_ref)
             print(f"precision {prec} tile {t}: rel L2 object {err:.3e} pupil {perr:.3e}", flush=True)
             assert err <= TOL_MFMA and perr <= TOL_MFMA, (prec, t)
-            check_windows(orc, descs[t], mout[t][0], o_ref, TOL_WIN_MFMA[prec],
+            check_windows(orc, descs[t], stacks[t], mout[t][0], o_ref, TOL_WIN_MFMA[prec],
                           f"precision {prec} tile {t}")

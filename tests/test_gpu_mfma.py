@@ -64,7 +64,9 @@ def test_single_tile_mfma_matches_oracle(fpm, orc, prec):
           f"pupil {rel(P, P_ref):.3e}")
     assert err <= TOL_MFMA
     assert rel(P, P_ref) <= TOL_MFMA
-    check_windows(orc, td.desc, o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec}")
+    check_windows(orc, td.desc, I, o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec}")
+    print(f"precision {prec}: residual history max rel dev "
+          f"{float(np.max(np.abs(r - r_ref) / np.abs(r_ref))):.2e}")
     assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9)
 
 
@@ -88,7 +90,9 @@ def test_full_field_tiles_mfma_match_oracle(fpm, orc, prec):
     for t, ((o, P, r), (o_ref, P_ref, r_ref)) in enumerate(zip(out, refs)):
         assert errs[t] <= TOL_MFMA, t
         assert rel(P, P_ref) <= TOL_MFMA, t
-        check_windows(orc, descs[t], o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec} tile {t}")
+        check_windows(orc, descs[t], Is[t], o, o_ref, TOL_WIN_MFMA[prec], f"precision {prec} tile {t}")
+        print(f"precision {prec} tile {t}: residual history max rel dev "
+              f"{float(np.max(np.abs(r - r_ref) / np.abs(r_ref))):.2e}")
         assert np.allclose(r, r_ref, rtol=RES_RTOL[prec], atol=1e-9), t
 
 
@@ -115,7 +119,7 @@ def test_mixed_precisions_and_sizes_in_one_plan(fpm, orc):
         err = rel(out[t][0], o_ref)
         print(f"tile {t} n {d.n} precision {d.precision}: rel L2 {err:.3e}")
         assert err <= (TOL_FP32 if d.precision == 0 else TOL_MFMA), t
-        check_windows(orc, d, out[t][0], o_ref,
+        check_windows(orc, d, Is[t], out[t][0], o_ref,
                       TOL_WIN_FP32 if d.precision == 0 else TOL_WIN_MFMA[d.precision],
                       f"tile {t} precision {d.precision}")
     alone = run_gpu(fpm, [descs[0]], [Is[0]])[0]
@@ -145,4 +149,4 @@ def test_mfma_edge_cases(fpm, orc):
             assert np.all(o == 0), t
         else:
             assert rel(o, o_ref) <= TOL_MFMA, t
-            check_windows(orc, dd, o, o_ref, TOL_WIN_MFMA[dd.precision], f"edge case {t}")
+            check_windows(orc, dd, II, o, o_ref, TOL_WIN_MFMA[dd.precision], f"edge case {t}")

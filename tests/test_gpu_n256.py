@@ -75,7 +75,7 @@ def test_n256_tile_matches_oracle(fpm, orc, schedule, pupil):
     print(f"n=256 schedule {schedule} pupil {pupil}: rel L2 {err:.3e}")
     assert err <= TOL_OBJ
     assert rel(P, P_ref) <= TOL_OBJ
-    check_windows(orc, td.desc, o, o_ref, TOL_WIN, f"n=256 schedule {schedule}")
+    check_windows(orc, td.desc, I, o, o_ref, TOL_WIN, f"n=256 schedule {schedule}")
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
 
@@ -101,7 +101,7 @@ def test_n256_mixed_with_smaller_tiles(fpm, orc):
         err = rel(out[t][0], o_ref)
         print(f"tile {t} n {d.n}: rel L2 {err:.3e}")
         assert err <= TOL_OBJ, t
-        check_windows(orc, d, out[t][0], o_ref, TOL_WIN, f"tile {t}")
+        check_windows(orc, d, Is[t], out[t][0], o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(out[t][2], r_ref, rtol=1e-4, atol=1e-9), t
 
 

@@ -130,7 +130,7 @@ def test_online_raster_arrival_matches_oracle(fpm, orc, start):
         tol = TOL_FP32 if d.precision == 0 else TOL_MFMA
         print(f"tile {t} n {d.n} precision {d.precision}: rel L2 object {err:.3e} pupil {perr:.3e}")
         assert err <= tol and perr <= tol, t
-        check_windows(orc, d, out[t][0], o_ref,
+        check_windows(orc, d, Is[t], out[t][0], o_ref,
                       1e-3 if d.precision == 0 else TOL_WIN_MFMA[d.precision], f"tile {t}")
         assert np.allclose(out[t][2], r.residual, rtol=1e-2 if d.precision else 1e-4, atol=1e-9), t
 

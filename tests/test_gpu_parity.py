@@ -87,7 +87,7 @@ def test_single_tile_sequential_matches_oracle(fpm, orc):
     err = rel(o, o_ref)
     print("single-tile rel L2 object error vs oracle:", err)
     assert err <= TOL_OBJ
-    check_windows(orc, td.desc, o, o_ref, TOL_WIN, "single tile")
+    check_windows(orc, td.desc, I, o, o_ref, TOL_WIN, "single tile")
     assert rel(P, P_ref) <= TOL_OBJ
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
@@ -110,7 +110,7 @@ def test_multi_tile_schedules_match_oracle(fpm, orc, schedule, pupil):
         err = rel(o, o_ref)
         print(f"tile {t} schedule {schedule} pupil {pupil}: rel L2 {err:.3e}")
         assert err <= TOL_OBJ
-        check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
+        check_windows(orc, d, Is[t], o, o_ref, TOL_WIN, f"tile {t}")
         assert rel(P, P_ref) <= TOL_OBJ
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
@@ -179,7 +179,7 @@ def test_mixed_sizes_and_edge_cases(fpm, orc):
             assert np.all(o == 0), t
         else:
             assert rel(o, o_ref) <= TOL_OBJ, t
-            check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
+            check_windows(orc, d, Is[t], o, o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
@@ -196,7 +196,7 @@ def test_large_board_far_leds_match_oracle(fpm, orc):
     assert np.all(np.isfinite(o)) and np.all(np.isfinite(r))
     o_ref, P_ref, r_ref = oracle_run(orc, d, I)
     assert rel(o, o_ref) <= TOL_OBJ
-    check_windows(orc, d, o, o_ref, TOL_WIN, "21x21 board")
+    check_windows(orc, d, I, o, o_ref, TOL_WIN, "21x21 board")
     assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9)
 
 
@@ -227,7 +227,7 @@ def test_uneven_batch_matches_oracle(fpm, orc):
         err = rel(o, o_ref)
         print(f"tile {t} n {d.n} grid {d.led_rows} up {d.upsample}: rel L2 {err:.3e}")
         assert err <= TOL_OBJ, t
-        check_windows(orc, d, o, o_ref, TOL_WIN, f"tile {t}")
+        check_windows(orc, d, Is[t], o, o_ref, TOL_WIN, f"tile {t}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
@@ -273,17 +273,19 @@ def test_uneven_tiles_at_drawn_iterations_match_oracle(fpm, orc):
               f"rel L2 {err:.3e}, pupil {rel(P, P_ref):.3e}")
         assert err <= TOL_OBJ, t
         assert rel(P, P_ref) <= TOL_OBJ, t
-        check_windows(orc, d, o, o_ref, TOL_WIN, f"n {d.n}")
+        check_windows(orc, d, Is[t], o, o_ref, TOL_WIN, f"n {d.n}")
         assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
 
 
 @pytest.mark.parametrize("n", [64, 96, 128])
 def test_update_variants(fpm, orc, monkeypatch, n):
     """The autotuner's variants: 4 or 8 lanes per line, LDS row padding, one
-    or several rounds of lines per workgroup (6, 7: two and four rounds).
-    Variants of one lane count differ only in layout and give the same bits;
-    the 8-lane form orders its floating-point steps differently and must meet
-    the same tolerance against the oracle."""
+    or several rounds of lines per workgroup (6, 7: 8 lanes in two and four
+    rounds, with the fused cross-lane steps; 8: 4 lanes in two rounds).
+    Variants of one lane count differ only in layout (and in how the 8-lane
+    cross-lane steps are issued) and give the same bits; the 8-lane form
+    orders its floating-point steps differently and must meet the same
+    tolerance against the oracle."""
     rng = np.random.default_rng(n)
     descs, Is = [], []
     for k in range(2):
@@ -296,10 +298,10 @@ def test_update_variants(fpm, orc, monkeypatch, n):
         Is.append(I)
     refs = [oracle_run(orc, d, I) for d, I in zip(descs, Is)]
     first = {}
-    for v in range(8):
+    for v in range(9):
         monkeypatch.setenv("FPM_UPDATE_VARIANT", str(v))
         _, out = run_gpu(fpm, descs, Is)
-        fam = 4 if v < 4 else 8
+        fam = 4 if v < 4 or v == 8 else 8
         if fam not in first:
             first[fam] = out
             for (o, _, r), (o_ref, _, r_ref) in zip(out, refs):
@@ -366,5 +368,5 @@ def test_pipelined_equals_sequential_bitwise(fpm, orc, pupil):
     for t, d in enumerate(descs):
         o_ref, _, r_ref = oracle_run(orc, d, Is[t])
         assert rel(pip[t][0], o_ref) <= TOL_OBJ
-        check_windows(orc, d, pip[t][0], o_ref, TOL_WIN, f"pipelined tile {t}")
+        check_windows(orc, d, Is[t], pip[t][0], o_ref, TOL_WIN, f"pipelined tile {t}")
         assert np.allclose(pip[t][2], r_ref, rtol=1e-4, atol=1e-9)

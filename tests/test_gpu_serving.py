@@ -57,7 +57,7 @@ def test_alone_equals_mix_and_matches_oracle(fpm, orc):
             o_ref = orc.spectrum_to_object(d, r.S)
             err = np.linalg.norm(alone[0] - o_ref) / np.linalg.norm(o_ref)
             assert err <= TOL_OBJ, (k, err)
-            check_windows(orc, d, alone[0], o_ref, 1e-3, f"request {k}")
+            check_windows(orc, d, I.reshape(d.L, d.n, d.n), alone[0], o_ref, 1e-3, f"request {k}")
             assert np.allclose(alone[2], r.residual, rtol=1e-4, atol=1e-9)
 
 
