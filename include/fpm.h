@@ -290,6 +290,22 @@ fpm_status fpm_estimate_defocus(const fpm_tile_desc *tiles, int32_t ntiles,
 fpm_status fpm_stitch(const void *tiles, int32_t rows, int32_t cols, int32_t side,
                       int32_t overlap, void *out, fpm_mem where, void *hip_stream);
 
+/* fpm_stitch without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same layout, arithmetic and result bits as fpm_stitch,
+ * device memory only: `tiles` and `out` are device pointers the caller owns.
+ * The strip sums and factors live in a fixed scratch array of each device,
+ * sized for at most 4096 tiles (rows * cols) and held until the process
+ * ends; it allocates, frees and synchronises nothing, and returns once the
+ * kernels are enqueued on hip_stream (`out` is written when the stream
+ * reaches them).  All calls on one device share that scratch: calls whose
+ * work overlaps on one device (different streams, no ordering between them)
+ * race and must be ordered by the caller.  Errors: FPM_E_ARG (NULL, grid,
+ * side or overlap out of range, more than 4096 tiles), FPM_E_DEVICE (the
+ * scratch lookup or a launch failed); `out` is untouched on error. */
+fpm_status fpm_stitch_noalloc(const void *tiles, int32_t rows, int32_t cols, int32_t side,
+                              int32_t overlap, void *out, void *hip_stream);
+
 /* Per-kind kernel timing of one reconstruction (profiling aid). */
 typedef enum {
   FPM_KERNEL_UPDATE = 0,      /* fused LED-tile update (the hot loop)          */

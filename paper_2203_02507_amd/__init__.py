@@ -39,7 +39,7 @@ EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_table
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
            "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch",
-           "fpm_estimate_defocus",
+           "fpm_stitch_noalloc", "fpm_estimate_defocus",
            "fpm_online_begin", "fpm_online_push", "fpm_online_finish", "fpm_online_abort")
 
 
@@ -123,6 +123,8 @@ def _load():
     L.fpm_profile_reconstruct.restype = C.c_int
     L.fpm_stitch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int, vp]
     L.fpm_stitch.restype = C.c_int
+    L.fpm_stitch_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+    L.fpm_stitch_noalloc.restype = C.c_int
     L.fpm_estimate_defocus.argtypes = [C.POINTER(TileDescC), C.c_int32, vp, C.c_int, C.c_double,
                                        C.c_double, C.c_double, C.c_int32, vp, vp, C.c_int32, vp]
     L.fpm_estimate_defocus.restype = C.c_int
@@ -360,6 +362,18 @@ def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where:
     return check(lib.fpm_stitch(_buf(tiles, where, "c64", count, "tiles"), rows, cols, side,
                                 overlap, _buf(out, where, "c64", H * W, "out"),
                                 where, _stream(stream)))
+
+
+def fpm_stitch_noalloc(tiles, rows: int, cols: int, side: int, overlap: int, out,
+                       stream=None) -> int:
+    """fpm_stitch on device buffers with the library's fixed scratch (no
+    allocation; at most 4096 tiles; returns once enqueued on `stream`)."""
+    ok = rows > 0 and cols > 0 and side > 0 and 0 <= overlap < side
+    H, W = stitched_shape(rows, cols, side, overlap) if ok else (0, 0)
+    count = rows * cols * side * side if ok else 0
+    return check(lib.fpm_stitch_noalloc(
+        _buf(tiles, FPM_MEM_DEVICE, "c64", count, "tiles"), rows, cols, side, overlap,
+        _buf(out, FPM_MEM_DEVICE, "c64", H * W, "out"), _stream(stream)))
 
 
 def defocus_candidates(z_lo: float, z_hi: float, z_step: float) -> int:

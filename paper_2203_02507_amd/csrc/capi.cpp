@@ -349,6 +349,35 @@ fpm_status fpm_stitch(const void* tiles, int32_t rows, int32_t cols, int32_t sid
 }
 FPM_ABI_GUARD("fpm_stitch")
 
+fpm_status fpm_stitch_noalloc(const void* tiles, int32_t rows, int32_t cols, int32_t side,
+                              int32_t overlap, void* out, void* hip_stream) try {
+  if (!tiles || !out) return fail(FPM_E_ARG, "fpm_stitch_noalloc: NULL argument");
+  if (rows < 1 || cols < 1 || side < 2 || side > 65536 || overlap < 0 || 2 * overlap > side)
+    return fail(FPM_E_ARG,
+                "fpm_stitch_noalloc: grid, side or overlap out of range (0 <= overlap <= side/2)");
+  if ((int64_t)rows * cols > kStitchNoAllocMaxTiles)
+    return fail(FPM_E_ARG, "fpm_stitch_noalloc: more than " +
+                               std::to_string(kStitchNoAllocMaxTiles) +
+                               " tiles (the fixed scratch holds at most that many); use fpm_stitch");
+  const int64_t W = (int64_t)cols * (side - overlap) + overlap;
+  const int64_t H = (int64_t)rows * (side - overlap) + overlap;
+  if (W * H > ((int64_t)1 << 34)) return fail(FPM_E_ARG, "fpm_stitch_noalloc: output too large");
+  if (stitch_scratch_bytes(rows, cols) > kStitchNoAllocBytes)
+    return fail(FPM_E_ARG, "fpm_stitch_noalloc: scratch too small for the grid");
+  void* scratch = nullptr;
+  fpm_status st = FPM_OK;
+  if (!hip_ok(stitch_noalloc_scratch(&scratch), "hipGetSymbolAddress(stitch scratch)", &st))
+    return st;
+  // every scratch word a call reads is written earlier in the same call, so
+  // nothing needs clearing between calls
+  if (!hip_ok(launch_stitch((const float2*)tiles, rows, cols, side, overlap, (float2*)out,
+                            scratch, (hipStream_t)hip_stream),
+              "stitch kernels", &st))
+    return st;
+  return FPM_OK;
+}
+FPM_ABI_GUARD("fpm_stitch_noalloc")
+
 fpm_status fpm_forward(fpm_plan_t* plan, const void* object, const void* pupil, float* intensity,
                        fpm_mem where, void* hip_stream) try {
   if (!plan || !object || !intensity || (where != FPM_MEM_HOST && where != FPM_MEM_DEVICE))

@@ -161,4 +161,12 @@ namespace fpm {
 size_t stitch_scratch_bytes(int rows, int cols);
 hipError_t launch_stitch(const float2* tiles, int rows, int cols, int side, int overlap,
                          float2* out, void* scratch, hipStream_t st);
+// The allocation-free stitch keeps its scratch in a fixed device array of
+// kStitchNoAllocBytes per device (enough for kStitchNoAllocMaxTiles tiles:
+// 88 bytes per tile plus 256); stitch_noalloc_scratch returns the current
+// device's copy, looked up on the first call on that device.
+constexpr int kStitchNoAllocMaxTiles = 4096;
+constexpr size_t kStitchNoAllocBytes = (size_t)kStitchNoAllocMaxTiles * 88 + 256;
+constexpr int kMaxDevices = 64;
+hipError_t stitch_noalloc_scratch(void** ptr);
 }  // namespace fpm

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "fpm_internal.h"
 
@@ -138,10 +139,38 @@ __global__ __launch_bounds__(256) void stitch_compose_kernel(const float2* __res
   out[(size_t)Y * W + X] = make_float2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
 }
 
+// Scratch of the allocation-free stitch (fpm_stitch_noalloc): the strip
+// sums, row factors and tile factors of at most kStitchNoAllocMaxTiles tiles,
+// in one array per device that lives until the process ends.  Host code
+// never uses this name as an address: stitch_noalloc_scratch() looks up each
+// device's copy once and hands that pointer to the kernels.
+static_assert(4 * sizeof(D2) + sizeof(D2) + sizeof(float2) == 88,
+              "per-tile scratch bytes of the allocation-free stitch");
+static __device__ __align__(256) unsigned char scratch[kStitchNoAllocBytes];
+
 }  // namespace
 
 size_t stitch_scratch_bytes(int rows, int cols) {
   return (size_t)rows * cols * (4 * sizeof(D2) + sizeof(D2) + sizeof(float2)) + 256;
+}
+
+hipError_t stitch_noalloc_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* per_device[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!per_device[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    per_device[dev] = p;
+  }
+  *ptr = per_device[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_stitch(const float2* tiles, int rows, int cols, int side, int overlap,
