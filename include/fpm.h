@@ -191,11 +191,14 @@ fpm_status fpm_forward(fpm_plan_t *plan, const void *object, const void *pupil,
  *   object_out    complex64 [tile][N][N]: up^2 * IFFT_N(shift S); may be NULL.
  *   pupil_out     complex64 [tile][n][n]; may be NULL.
  *   residual_out  double [tile][iterations]; may be NULL.
- * `where` applies to all four buffers.  FPM_MEM_DEVICE: enqueued on
- * `hip_stream`, returns without waiting (intensities are not validated).
- * FPM_MEM_HOST: the intensities are validated (FPM_E_ARG on NaN, Inf or a
- * negative value), copied, and the call synchronises; FPM_E_DIVERGED if a
- * residual is not finite.
+ * `where` applies to all four buffers.  FPM_MEM_HOST: the intensities are
+ * validated (FPM_E_ARG on NaN, Inf or a negative value), copied, and the call
+ * synchronises; FPM_E_DIVERGED if a residual is not finite.  On either error
+ * no output is written.  FPM_MEM_DEVICE: enqueued on `hip_stream`, returns
+ * without waiting; the intensities are checked on the device before the
+ * sweep and the residuals after it, and if either check fails the outputs
+ * are not written; fpm_plan_status reports the outcome (FPM_E_ARG or
+ * FPM_E_DIVERGED) once the work has run.
  * The plan's tiles run as independent chains on streams of the library's
  * own, forked from `hip_stream` and joined back into it with events, so the
  * work is ordered on `hip_stream` as one operation; FPM_CHAINS=1..4 sets the
@@ -305,6 +308,15 @@ fpm_status fpm_stitch(const void *tiles, int32_t rows, int32_t cols, int32_t sid
  * scratch lookup or a launch failed); `out` is untouched on error. */
 fpm_status fpm_stitch_noalloc(const void *tiles, int32_t rows, int32_t cols, int32_t side,
                               int32_t overlap, void *out, void *hip_stream);
+
+/* Outcome of the plan's last device-mode fpm_reconstruct (or online
+ * session): waits until that call's work has run, then sets *status to
+ * FPM_OK, FPM_E_ARG (a negative or non-finite intensity) or FPM_E_DIVERGED
+ * (a residual that is not finite); in both error cases the call wrote no
+ * output, and fpm_last_error says which.  Host-mode calls report their own
+ * errors and leave FPM_OK here.  Returns FPM_E_ARG for NULL arguments,
+ * FPM_E_DEVICE if the wait or the read fails. */
+fpm_status fpm_plan_status(fpm_plan_t *plan, fpm_status *status);
 
 /* Per-kind kernel timing of one reconstruction (profiling aid). */
 typedef enum {

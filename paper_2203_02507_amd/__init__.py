@@ -39,7 +39,7 @@ EXPORTS = ("fpm_plan", "fpm_plan_destroy", "fpm_plan_tile_info", "fpm_plan_table
            "fpm_plan_device_bytes", "fpm_forward", "fpm_reconstruct", "fpm_server_create",
            "fpm_server_destroy", "fpm_submit", "fpm_poll", "fpm_wait", "fpm_cancel",
            "fpm_last_error", "fpm_version", "fpm_profile_reconstruct", "fpm_stitch",
-           "fpm_stitch_noalloc", "fpm_estimate_defocus",
+           "fpm_stitch_noalloc", "fpm_estimate_defocus", "fpm_plan_status",
            "fpm_online_begin", "fpm_online_push", "fpm_online_finish", "fpm_online_abort")
 
 
@@ -128,6 +128,8 @@ def _load():
     L.fpm_estimate_defocus.argtypes = [C.POINTER(TileDescC), C.c_int32, vp, C.c_int, C.c_double,
                                        C.c_double, C.c_double, C.c_int32, vp, vp, C.c_int32, vp]
     L.fpm_estimate_defocus.restype = C.c_int
+    L.fpm_plan_status.argtypes = [vp, C.POINTER(C.c_int)]
+    L.fpm_plan_status.restype = C.c_int
     L.fpm_online_begin.argtypes = [vp, vp]
     L.fpm_online_begin.restype = C.c_int
     L.fpm_online_push.argtypes = [vp, C.c_int32, vp, C.c_int, vp]
@@ -349,6 +351,14 @@ def fpm_profile_reconstruct(plan: Plan, intensity, stream=None) -> dict:
     return {name: {"launches": out[i].launches, "items": out[i].items,
                    "total_ms": out[i].total_ms, "busy_ms": out[i].busy_ms}
             for i, name in enumerate(KERNEL_KINDS)}
+
+
+def fpm_plan_status(plan: "Plan") -> int:
+    """Outcome of the plan's last device-mode call (FPM_OK, FPM_E_ARG or
+    FPM_E_DIVERGED), once its work has run."""
+    st = C.c_int(0)
+    check(lib.fpm_plan_status(plan.handle, C.byref(st)))
+    return st.value
 
 
 def fpm_stitch(tiles, rows: int, cols: int, side: int, overlap: int, out, where: int,

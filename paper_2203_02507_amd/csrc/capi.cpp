@@ -81,65 +81,92 @@ fpm_status mark_done(fpm_plan_t* p, hipStream_t s) {
   return FPM_OK;
 }
 
+// The plan's device status word, allocated on first use and cleared for
+// this call.
+fpm_status clear_status(Executor& ex, hipStream_t s) {
+  fpm_status st = FPM_OK;
+  if (!hip_ok(ex.status_d.alloc(16), "hipMalloc(status)", &st) ||
+      !hip_ok(launch_status_clear((int*)ex.status_d.p, s), "clear status", &st))
+    return st;
+  return FPM_OK;
+}
+
 // Object (finalised), pupil and residual history of every tile into the
-// caller's buffers; host mode synchronises and checks the residuals.
+// caller's buffers, and nothing of them when the call failed.
+//   Host mode: the residuals come back first; if one is not finite the call
+//   returns FPM_E_DIVERGED with no output written, else the outputs are
+//   copied and the stream synchronised.
+//   Device mode: the residuals are checked on the device into the plan's
+//   status word (with the intensity check run before the sweep), and every
+//   output is copied by a kernel that writes nothing when that word is set;
+//   fpm_plan_status reports it once the work has run.
 fpm_status collect_outputs(fpm_plan_t* plan, fpm_mem where, void* object_out, void* pupil_out,
                            double* residual_out, hipStream_t s) {
   Executor& ex = plan->exec;
   fpm_status st = FPM_OK;
-  const hipMemcpyKind d2o = where == FPM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  const TileDev* tab = (const TileDev*)ex.table.p;
+  int* status = (int*)ex.status_d.p;
+  if (!hip_ok(ex.res_stage.alloc(sizeof(double) * std::max<int64_t>(1, ex.total_res)), "hipMalloc",
+              &st) ||
+      !hip_ok(launch_gather(tab, ex.ntiles, ex.res_stage.p, (const int64_t*)ex.r_off_d.p, 3,
+                            ex.n_max, s),
+              "gather residual", &st))
+    return st;
+  if (where == FPM_MEM_HOST) {
+    std::vector<double> res_host(std::max<int64_t>(1, ex.total_res));
+    if (!hip_ok(hipMemcpyAsync(res_host.data(), ex.res_stage.p, sizeof(double) * ex.total_res,
+                               hipMemcpyDeviceToHost, s),
+                "D2H residual", &st) ||
+        !hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st))
+      return st;
+    for (int64_t i = 0; i < ex.total_res; ++i)
+      if (!std::isfinite(res_host[i]))
+        return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
+    if (object_out) {
+      if (!hip_ok(ex.enqueue_finalize(s), "finalise", &st) ||
+          !hip_ok(hipMemcpyAsync(object_out, ex.obj_stage.p, sizeof(float2) * ex.total_obj,
+                                 hipMemcpyDeviceToHost, s),
+                  "copy object", &st))
+        return st;
+    }
+    if (pupil_out) {
+      if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
+          !hip_ok(launch_gather(tab, ex.ntiles, ex.pupil_stage.p, (const int64_t*)ex.p_off_d.p, 1,
+                                ex.n_max, s),
+                  "gather pupil", &st) ||
+          !hip_ok(hipMemcpyAsync(pupil_out, ex.pupil_stage.p, sizeof(float2) * ex.total_pupil,
+                                 hipMemcpyDeviceToHost, s),
+                  "copy pupil", &st))
+        return st;
+    }
+    if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
+    if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
+    return FPM_OK;
+  }
+  if (!hip_ok(launch_check_residuals(tab, ex.ntiles, status, s), "check residuals", &st))
+    return st;
   if (object_out) {
     if (!hip_ok(ex.enqueue_finalize(s), "finalise", &st) ||
-        !hip_ok(hipMemcpyAsync(object_out, ex.obj_stage.p, sizeof(float2) * ex.total_obj, d2o, s),
+        !hip_ok(launch_copy_if_ok(object_out, ex.obj_stage.p,
+                                  (int64_t)sizeof(float2) * ex.total_obj, status, s),
                 "copy object", &st))
       return st;
   }
   if (pupil_out) {
-    if (where == FPM_MEM_DEVICE) {
-      if (!hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, pupil_out,
-                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
-                  "gather pupil", &st))
-        return st;
-    } else {
-      if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
-          !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.pupil_stage.p,
-                                (const int64_t*)ex.p_off_d.p, 1, ex.n_max, s),
-                  "gather pupil", &st) ||
-          !hip_ok(hipMemcpyAsync(pupil_out, ex.pupil_stage.p, sizeof(float2) * ex.total_pupil,
-                                 d2o, s),
-                  "copy pupil", &st))
-        return st;
-    }
-  }
-  std::vector<double> res_host;
-  const bool want_res_host = where == FPM_MEM_HOST;
-  if (residual_out || want_res_host) {
-    if (!hip_ok(ex.res_stage.alloc(sizeof(double) * std::max<int64_t>(1, ex.total_res)),
-                "hipMalloc", &st) ||
-        !hip_ok(launch_gather((const TileDev*)ex.table.p, ex.ntiles, ex.res_stage.p,
-                              (const int64_t*)ex.r_off_d.p, 3, ex.n_max, s),
-                "gather residual", &st))
+    if (!hip_ok(ex.pupil_stage.alloc(sizeof(float2) * ex.total_pupil), "hipMalloc", &st) ||
+        !hip_ok(launch_gather(tab, ex.ntiles, ex.pupil_stage.p, (const int64_t*)ex.p_off_d.p, 1,
+                              ex.n_max, s),
+                "gather pupil", &st) ||
+        !hip_ok(launch_copy_if_ok(pupil_out, ex.pupil_stage.p,
+                                  (int64_t)sizeof(float2) * ex.total_pupil, status, s),
+                "copy pupil", &st))
       return st;
-    if (residual_out && where == FPM_MEM_DEVICE &&
-        !hip_ok(hipMemcpyAsync(residual_out, ex.res_stage.p, sizeof(double) * ex.total_res,
-                               hipMemcpyDeviceToDevice, s),
-                "copy residual", &st))
-      return st;
-    if (want_res_host) {
-      res_host.resize(std::max<int64_t>(1, ex.total_res));
-      if (!hip_ok(hipMemcpyAsync(res_host.data(), ex.res_stage.p, sizeof(double) * ex.total_res,
-                                 hipMemcpyDeviceToHost, s),
-                  "copy residual", &st))
-        return st;
-    }
   }
-  if (where == FPM_MEM_HOST) {
-    if (!hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize", &st)) return st;
-    for (int64_t i = 0; i < ex.total_res; ++i)
-      if (!std::isfinite(res_host[i]))
-        return fail(FPM_E_DIVERGED, "fpm_reconstruct: residual became non-finite");
-    if (residual_out) std::memcpy(residual_out, res_host.data(), sizeof(double) * ex.total_res);
-  }
+  if (residual_out &&
+      !hip_ok(launch_copy_if_ok(residual_out, ex.res_stage.p,
+                                (int64_t)sizeof(double) * ex.total_res, status, s),
+              "copy residual", &st))
+    return st;
   return FPM_OK;
 }
 
@@ -439,12 +466,16 @@ fpm_status fpm_reconstruct(fpm_plan_t* plan, const float* intensity, fpm_mem whe
   Executor& ex = plan->exec;
   hipStream_t s = (hipStream_t)hip_stream;
   if ((st = order_after_previous(plan, s)) != FPM_OK) return st;
+  if ((st = clear_status(ex, s)) != FPM_OK) return st;
   const size_t int_bytes = sizeof(float) * ex.total_I;
   const float* I = intensity;
   if (where == FPM_MEM_HOST) {
     if (!hip_ok(ex.I_stage.alloc(int_bytes), "hipMalloc(intensity stage)", &st)) return st;
     if ((st = stage_host_intensities(ex, intensity, s)) != FPM_OK) return st;
     I = (const float*)ex.I_stage.p;
+  } else if (!hip_ok(launch_validate_intensity(intensity, ex.total_I, (int*)ex.status_d.p, s),
+                     "validate intensity", &st)) {
+    return st;
   }
   if (!hip_ok(launch_set_intensity((TileDev*)ex.table.p, ex.ntiles, I,
                                    (const int64_t*)ex.i_off_d.p, s),
@@ -487,6 +518,7 @@ fpm_status fpm_online_begin(fpm_plan_t* plan, void* hip_stream) try {
                                    (const int64_t*)ex.i_off_d.p, s),
               "bind online stack", &st))
     return st;
+  if ((st = clear_status(ex, s)) != FPM_OK) return st;
   ex.online_pushed.assign(L, 0);
   ex.online_count = 0;
   return mark_done(plan, s);
@@ -530,6 +562,10 @@ fpm_status fpm_online_push(fpm_plan_t* plan, int32_t led, const float* intensity
       return st;
     ex.online_ev_armed = true;
     src = (const float*)ex.online_stage.p;
+  } else if (!hip_ok(launch_validate_intensity(intensity, ex.online_push_floats,
+                                               (int*)ex.status_d.p, s),
+                     "validate image", &st)) {
+    return st;
   }
   TileDev* tab = (TileDev*)ex.table.p;
   if (!hip_ok(launch_online_scatter(tab, ex.ntiles, src, (const int64_t*)ex.online_src_off_d.p,
@@ -621,6 +657,32 @@ fpm_status fpm_online_abort(fpm_plan_t* plan) try {
   return FPM_OK;
 }
 FPM_ABI_GUARD("fpm_online_abort")
+
+fpm_status fpm_plan_status(fpm_plan_t* plan, fpm_status* status) try {
+  if (!plan || !status) return fail(FPM_E_ARG, "fpm_plan_status: NULL argument");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  *status = FPM_OK;
+  if (plan->device < 0 || !plan->exec.status_d.p) return FPM_OK;  // nothing has run
+  DeviceGuard g(plan);
+  if (!g.ok) return fail(FPM_E_DEVICE, "fpm_plan_status: cannot select the plan's device");
+  fpm_status st = FPM_OK;
+  if (plan->done_armed &&
+      !hip_ok(hipEventSynchronize(plan->done_ev), "hipEventSynchronize(last call)", &st))
+    return st;
+  int word = 0;
+  if (!hip_ok(hipMemcpy(&word, plan->exec.status_d.p, sizeof word, hipMemcpyDeviceToHost),
+              "read status", &st))
+    return st;
+  if (word & 1) {
+    *status = FPM_E_ARG;
+    g_last_error = "device-mode call: an intensity is negative or not finite (no output written)";
+  } else if (word & 2) {
+    *status = FPM_E_DIVERGED;
+    g_last_error = "device-mode call: a residual became non-finite (no output written)";
+  }
+  return FPM_OK;
+}
+FPM_ABI_GUARD("fpm_plan_status")
 
 fpm_status fpm_profile_reconstruct(fpm_plan_t* plan, const float* intensity,
                                    fpm_kernel_time* out, void* hip_stream) try {

@@ -139,6 +139,14 @@ hipError_t launch_online_scatter(const TileDev* table, int count, const float* s
 hipError_t launch_set_j0(TileDev* table, int count, int j0, hipStream_t st);
 // dst[off[t] + i] = tile t's pupil (which = 1), initial pupil (which = 2) or
 // residual history (which = 3, doubles)
+// Device-mode status word (bit 0: a negative or non-finite intensity, bit 1:
+// a residual that is not finite): cleared by a kernel, set by the checks;
+// copy_if_ok copies `bytes` only while the word is 0.
+hipError_t launch_status_clear(int* status, hipStream_t st);
+hipError_t launch_validate_intensity(const float* I, int64_t count, int* status, hipStream_t st);
+hipError_t launch_check_residuals(const TileDev* tiles, int count, int* status, hipStream_t st);
+hipError_t launch_copy_if_ok(void* dst, const void* src, int64_t bytes, const int* status,
+                             hipStream_t st);
 hipError_t launch_gather(const TileDev* tiles, int count, void* dst, const int64_t* off,
                          int which, int n_max, hipStream_t st);
 

@@ -1752,6 +1752,61 @@ __global__ void set_intensity_kernel(TileDev* __restrict__ table, int count,
   if (t < count) table[t].I = base + i_off[t];
 }
 
+// ============================================ device-mode status checks
+// Status word of a device-mode call: bit 0 a negative or non-finite
+// intensity, bit 1 a residual that is not finite.  Cleared by a kernel (no
+// memset node), set with atomic OR, read by the host later.
+__global__ void status_clear_kernel(int* __restrict__ status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *status = 0;
+}
+__global__ __launch_bounds__(256) void validate_intensity_kernel(const float* __restrict__ I,
+                                                                 int64_t count,
+                                                                 int* __restrict__ status) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+  for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < count; i += stride) {
+    if (i + 4 <= count) {
+      const float4 v = *reinterpret_cast<const float4*>(I + i);
+      // v >= 0 is false for NaN; v <= FLT_MAX is false for +Inf
+      bad |= !(v.x >= 0.0f && v.x <= 3.402823466e38f) || !(v.y >= 0.0f && v.y <= 3.402823466e38f) ||
+             !(v.z >= 0.0f && v.z <= 3.402823466e38f) || !(v.w >= 0.0f && v.w <= 3.402823466e38f);
+    } else {
+      for (int64_t k = i; k < count; ++k) bad |= !(I[k] >= 0.0f && I[k] <= 3.402823466e38f);
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, 1);
+}
+// one thread per tile: every residual of its history
+__global__ void check_residuals_kernel(const TileDev* __restrict__ tiles, int count,
+                                       int* __restrict__ status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const TileDev d = tiles[t];
+  bool bad = false;
+  for (int k = 0; k < d.iters; ++k) {
+    const double r = d.residual[k];
+    bad |= !(r == r) || r > 1.79e308 || r < -1.79e308;
+  }
+  if (bad) atomicOr(status, 2);
+}
+// dst <- src (bytes, 16-byte aligned both) unless the status word is set
+__global__ __launch_bounds__(256) void copy_if_ok_kernel(void* __restrict__ dst,
+                                                         const void* __restrict__ src,
+                                                         int64_t bytes,
+                                                         const int* __restrict__ status) {
+  if (*status != 0) return;
+  const int64_t n16 = bytes / 16;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * 256)
+    d4[i] = s4[i];
+  const unsigned char* sb = reinterpret_cast<const unsigned char*>(src);
+  unsigned char* db = reinterpret_cast<unsigned char*>(dst);
+  if (blockIdx.x == 0)
+    for (int64_t i = n16 * 16 + threadIdx.x; i < bytes; i += 256) db[i] = sb[i];
+}
+
 // ========================================================== launchers
 namespace {
 template <int n, int PAD = 16>
@@ -1907,13 +1962,13 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
     // 16 lanes per line (R = 16: no spills); variant 1: 8 lanes (R = 32)
     const int grid = xcd_grid(count) < kBigSlots ? xcd_grid(count) : kBigSlots;
     static_assert(kBigSlots % kXcds == 0, "whole XCD blocks of slots");
-    // variant 1: 8 lanes per line (R = 32); 3: 16 lanes with the fused
-    // cross-lane steps and support pruning (the same bits as the default up
-    // to the sign of exact zeros); otherwise 16 lanes, unfused
+    // variant 1: 8 lanes per line (R = 32); 2: 16 lanes, unfused cross-lane
+    // steps; otherwise 16 lanes with the fused steps and support pruning
+    // (the same bits as variant 2 up to the sign of exact zeros)
     if (variant == 1) {
       hipLaunchKernelGGL((update_kernel_big<256, 8>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);
-    } else if (variant != 3) {
+    } else if (variant == 2) {
       hipLaunchKernelGGL((update_kernel_big<256, 16>), dim3(grid), dim3(kBigThreads), 0, st, tiles,
                          items, count, big_scratch);
     } else {
@@ -2045,6 +2100,32 @@ hipError_t launch_set_intensity(TileDev* table, int count, const float* base, co
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(set_intensity_kernel, dim3((count + 255) / 256), dim3(256), 0, st, table, count,
                      base, i_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_clear(int* status, hipStream_t st) {
+  hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(64), 0, st, status);
+  return hipGetLastError();
+}
+hipError_t launch_validate_intensity(const float* I, int64_t count, int* status, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 1023) / 1024, 2048);
+  hipLaunchKernelGGL(validate_intensity_kernel, dim3((unsigned)blocks), dim3(256), 0, st, I, count,
+                     status);
+  return hipGetLastError();
+}
+hipError_t launch_check_residuals(const TileDev* tiles, int count, int* status, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_residuals_kernel, dim3((count + 255) / 256), dim3(256), 0, st, tiles,
+                     count, status);
+  return hipGetLastError();
+}
+hipError_t launch_copy_if_ok(void* dst, const void* src, int64_t bytes, const int* status,
+                             hipStream_t st) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((bytes / 16 + 255) / 256, 4096));
+  hipLaunchKernelGGL(copy_if_ok_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, bytes,
+                     status);
   return hipGetLastError();
 }
 

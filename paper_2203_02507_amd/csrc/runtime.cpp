@@ -36,10 +36,13 @@ std::map<int, int> g_variant;
 }  // namespace
 
 int update_variant(int n) {
-  if (const char* v = std::getenv("FPM_UPDATE_VARIANT")) {
-    const int k = std::atoi(v);
-    if (k >= 0 && k < kUpdateVariants) return k;
-  }
+  // FPM_UPDATE_VARIANT_<n> (one tile size), then FPM_UPDATE_VARIANT (all)
+  const std::string one = "FPM_UPDATE_VARIANT_" + std::to_string(n);
+  for (const char* name : {one.c_str(), "FPM_UPDATE_VARIANT"})
+    if (const char* v = std::getenv(name)) {
+      const int k = std::atoi(v);
+      if (k >= 0 && k < kUpdateVariants) return k;
+    }
   std::lock_guard<std::mutex> lk(g_variant_mu);
   auto it = g_variant.find(n);
   return it == g_variant.end() ? kDefaultUpdateVariant : it->second;
@@ -49,7 +52,9 @@ void set_update_variant(int n, int v) {
   g_variant[n] = v;
 }
 bool update_variant_known(int n) {
-  if (std::getenv("FPM_UPDATE_VARIANT")) return true;
+  if (std::getenv("FPM_UPDATE_VARIANT") ||
+      std::getenv(("FPM_UPDATE_VARIANT_" + std::to_string(n)).c_str()))
+    return true;
   std::lock_guard<std::mutex> lk(g_variant_mu);
   return g_variant.count(n) != 0;
 }

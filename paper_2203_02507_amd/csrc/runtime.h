@@ -94,6 +94,7 @@ struct Executor {
   int n_max = 0;
   // object finalise / forward staging: complex [total_obj], pupil [total_pupil]
   DevBuf obj_stage, fwd_P, fwd_table, fwd_items, I_stage, res_stage, pupil_stage;
+  DevBuf status_d;  // int: status word of the last device-mode call (see launch_status_clear)
   DevBuf big_scratch;  // transpose slots of the n = 256 kernels (allocated if used)
   std::vector<LineLaunch> fin_line_launches, fwd_line_launches;
   struct FwdLaunch {

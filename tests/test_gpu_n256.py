@@ -116,3 +116,27 @@ def test_n256_served_equals_planned(fpm, orc):
     assert st.status == fpm.FPM_OK
     _, ref = None, run_gpu(fpm, [td.desc], [I])[0]
     assert np.array_equal(out[0], ref[0])
+
+
+def test_n256_fused_form_bitwise(fpm, orc, monkeypatch):
+    """The 256-px kernel with fused cross-lane steps and support pruning
+    (the default) gives the bits of the unfused 16-lane form (variant 2) on
+    every schedule and pupil mode, and matches the oracle."""
+    tds = [tile256(41, schedule=1, pupil_update=1), tile256(42, schedule=0, pupil_update=1),
+           tile256(43, schedule=2, pupil_update=0, led_rows=13, led_cols=13)]
+    descs, Is = [], []
+    for td in tds:
+        _, _, I = orc.synthesize(td)
+        descs.append(td.desc)
+        Is.append(I)
+    outs = {}
+    for v in ("2", "7"):
+        monkeypatch.setenv("FPM_UPDATE_VARIANT_256", v)
+        print(f"variant {v}", flush=True)
+        outs[v] = run_gpu(fpm, descs, Is)
+    for a, b in zip(outs["2"], outs["7"]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for t, d in enumerate(descs):
+        o_ref, _, r_ref = oracle_run(orc, d, Is[t])
+        assert rel(outs["7"][t][0], o_ref) <= TOL_OBJ, t
+        assert np.allclose(outs["7"][t][2], r_ref, rtol=1e-4, atol=1e-9), t

@@ -370,3 +370,39 @@ def test_pipelined_equals_sequential_bitwise(fpm, orc, pupil):
         assert rel(pip[t][0], o_ref) <= TOL_OBJ
         check_windows(orc, d, Is[t], pip[t][0], o_ref, TOL_WIN, f"pipelined tile {t}")
         assert np.allclose(pip[t][2], r_ref, rtol=1e-4, atol=1e-9)
+
+
+def test_device_mode_errors_write_no_output(fpm, orc):
+    """Device mode checks its intensities before the sweep and its residuals
+    after it; on a failed check no output is written and fpm_plan_status
+    reports FPM_E_ARG or FPM_E_DIVERGED; host mode returns the same errors
+    with its outputs untouched; a good call afterwards is unaffected."""
+    import torch
+    td = fpm_synth.single_tile_64(iterations=2)[0]
+    _, _, I = orc.synthesize(td)
+    plan = fpm.Plan([td.desc])
+    nan_I = I.copy()
+    nan_I[11, 7, 9] = np.nan
+    big_I = I.copy()
+    big_I[5, 20, 0] = 3e38   # finite, but two of them in one lane's row segment
+    big_I[5, 20, 1] = 3e38   # overflow its FP32 residual partial: inf / inf
+    for bad, code in ((nan_I, fpm.FPM_E_ARG), (big_I, fpm.FPM_E_DIVERGED)):
+        print(f"device mode, expecting status {code}", flush=True)
+        obj = torch.full((plan.total_object * 2,), 7.0, dtype=torch.float32, device="cuda")
+        pup = torch.full((plan.total_pupil * 2,), 7.0, dtype=torch.float32, device="cuda")
+        res = torch.full((plan.total_residual,), 7.0, dtype=torch.float64, device="cuda")
+        fpm.fpm_reconstruct(plan, torch.from_numpy(bad.reshape(-1).copy()).cuda(),
+                            fpm.FPM_MEM_DEVICE, obj, pup, res)
+        assert fpm.fpm_plan_status(plan) == code
+        assert bool(torch.all(obj == 7.0)) and bool(torch.all(pup == 7.0))
+        assert bool(torch.all(res == 7.0))
+        o_h = np.full(plan.total_object * 2, 7.0, np.float32)
+        r_h = np.full(plan.total_residual, 7.0, np.float64)
+        with pytest.raises(fpm.FpmError) as e:
+            fpm.fpm_reconstruct(plan, bad.reshape(-1).copy(), fpm.FPM_MEM_HOST, o_h, None, r_h)
+        assert e.value.status == code
+        assert np.all(o_h == 7.0) and np.all(r_h == 7.0)
+    plan2, out = run_gpu(fpm, [td.desc], [I])
+    o_ref, _, r_ref = oracle_run(orc, td.desc, I)
+    assert rel(out[0][0], o_ref) <= TOL_OBJ
+    assert fpm.fpm_plan_status(plan2) == fpm.FPM_OK
