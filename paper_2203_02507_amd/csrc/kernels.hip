@@ -1249,6 +1249,16 @@ constexpr int kBigThreads = 512;
 
 // FUSED (Q = 16): the fused cross-lane steps and the support pruning Z of
 // update_kernel_rounds, with the same lane-sign bookkeeping (par16).
+// Transpose slot layout of update_kernel_big: blocks of four consecutive rows
+// of one support column, (row / 4, column, row % 4).  A wave of the row
+// phase then reads and writes 16 columns x 4 rows = 512 contiguous bytes per
+// instruction, and a column lane 4 rows = 32 contiguous bytes, instead of
+// 8-byte pieces 2 KB apart (each in a cache line of its own).
+template <int n>
+__device__ __forceinline__ size_t big_block(int c, int r) {
+  return ((size_t)(r >> 2) * n + c) * 4 + (r & 3);
+}
+
 template <int n, int Q, bool FUSED = false, int Z = 0>
 __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
                                                                  const Item* __restrict__ items,
@@ -1310,10 +1320,14 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
           line_dit<n, true, Q>(a, q, tw);
         }
-        float4* dst = reinterpret_cast<float4*>(sb + (size_t)line * n + xc);
+        // rows xc .. xc + R - 1 of support column `line`, four rows at a time
+        float4* dst = reinterpret_cast<float4*>(sb);
 #pragma unroll
-        for (int k = 0; k < R / 2; ++k)
-          dst[k] = make_float4(a[2 * k].x, a[2 * k].y, a[2 * k + 1].x, a[2 * k + 1].y);
+        for (int j = 0; j < R / 4; ++j) {
+          const size_t b = big_block<n>(line, xc + 4 * j) / 2;
+          dst[b] = make_float4(a[4 * j].x, a[4 * j].y, a[4 * j + 1].x, a[4 * j + 1].y);
+          dst[b + 1] = make_float4(a[4 * j + 2].x, a[4 * j + 2].y, a[4 * j + 3].x, a[4 * j + 3].y);
+        }
       }
     }
     pm = wave_max(pm);
@@ -1327,7 +1341,15 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       const int line = l0 + LPR * rd;
       int q = q_item;  // opaque per round: keeps twiddle reads inside the round
       asm volatile("" : "+v"(q));
-      load_rows<n, 0, Q, Z>(sb, t.kx0, t.nd, line, q, a);
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        if (p < Z || p >= R - Z) {  // outside every support column
+          a[p] = make_float2(0.0f, 0.0f);
+          continue;
+        }
+        const int c = q + Q * p - t.kx0;
+        a[p] = (c >= 0 && c < t.nd) ? sb[big_block<n>(c, line)] : make_float2(0.0f, 0.0f);
+      }
       if constexpr (FUSED)
         line_dit_f<n, true, 0, Z, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
       else
@@ -1352,7 +1374,7 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       for (int k = 0; k < R; ++k) {
         if (k < Z || k >= R - Z) continue;  // no support column there
         const int c = q + Q * k - t.kx0;
-        if (c >= 0 && c < t.nd) sb[(size_t)c * n + line] = a[k];
+        if (c >= 0 && c < t.nd) sb[big_block<n>(c, line)] = a[k];
       }
     }
     {
@@ -1375,12 +1397,15 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       int q = q_item;  // opaque per round: keeps twiddle reads inside the round
       asm volatile("" : "+v"(q));
       if (line < t.nd) {
-        const float4* src = reinterpret_cast<const float4*>(sb + (size_t)line * n + xc);
+        const float4* src = reinterpret_cast<const float4*>(sb);
 #pragma unroll
-        for (int k = 0; k < R / 2; ++k) {
-          const float4 f = src[k];
-          a[2 * k] = make_float2(f.x, f.y);
-          a[2 * k + 1] = make_float2(f.z, f.w);
+        for (int j = 0; j < R / 4; ++j) {
+          const size_t b = big_block<n>(line, xc + 4 * j) / 2;
+          const float4 f0 = src[b], f1 = src[b + 1];
+          a[4 * j] = make_float2(f0.x, f0.y);
+          a[4 * j + 1] = make_float2(f0.z, f0.w);
+          a[4 * j + 2] = make_float2(f1.x, f1.y);
+          a[4 * j + 3] = make_float2(f1.z, f1.w);
         }
         const int kx = t.kx0 + line;
         if constexpr (FUSED) {

@@ -242,11 +242,11 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     launches.push_back(l);
     init_ids = l;
   }
-  // Chains: the tiles are split into independent launch sequences, balanced
-  // by update count, that run on streams of their own; one chain's partial
-  // last wave of workgroups and its short group-mean launches then overlap
-  // the other chain's updates.  A tile's own launches keep their order, so
-  // the results do not depend on the split.
+  // Chains: the tiles are split into independent launch sequences that run on
+  // streams of their own; one chain's partial last wave of workgroups and its
+  // short group-mean launches then overlap the other chain's updates.  A
+  // tile's own launches keep their order, so the results do not depend on
+  // the split.
   std::vector<int> part_of(T, 0);
   {
     std::vector<int> ord(T);
@@ -256,10 +256,57 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
     std::vector<double> load(P, 0.0);
-    for (int t : ord) {
-      const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    // Whole (n, precision) classes go to chains of their own, largest class
+    // first: a class's launches then never wait behind another class's in
+    // stream order, and the sizes run side by side.  Chains left over after
+    // every class has one take tiles of the classes with the most work per
+    // chain, balanced by update count, so a single-class plan still splits
+    // over P chains.
+    std::map<std::pair<int, int>, double> ccost;
+    std::map<std::pair<int, int>, int> ccount;
+    for (int t = 0; t < T; ++t) {
+      ccost[{tiles[t].n, tiles[t].d.precision}] += cost(t);
+      ++ccount[{tiles[t].n, tiles[t].d.precision}];
+    }
+    std::vector<std::pair<double, std::pair<int, int>>> cs;
+    for (auto& kv : ccost) cs.push_back({kv.second, kv.first});
+    std::stable_sort(cs.begin(), cs.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int C = (int)cs.size();
+    std::map<std::pair<int, int>, std::vector<int>> chains_of;
+    const bool whole_classes = C >= P;
+    if (whole_classes) {
+      for (const auto& c : cs) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        chains_of[c.second] = {q};
+        load[q] += c.first;
+      }
+    } else {
+      // one chain per class, the rest to the classes with the most work per chain
+      // (never more chains than a class has tiles)
+      std::vector<int> nch(C, 1);
+      for (int extra = P - C; extra > 0; --extra) {
+        int best = -1;
+        for (int i = 0; i < C; ++i)
+          if (nch[i] < ccount[cs[i].second] &&
+              (best < 0 || cs[i].first / nch[i] > cs[best].first / nch[best]))
+            best = i;
+        if (best < 0) break;
+        ++nch[best];
+      }
+      int next = 0;
+      for (int i = 0; i < C; ++i)
+        for (int k = 0; k < nch[i]; ++k) chains_of[cs[i].second].push_back(next++);
+      P = next;
+      load.assign(P, 0.0);
+    }
+    for (int t : ord) {  // by cost, over the class's chains
+      const auto& mine = chains_of[{tiles[t].n, tiles[t].d.precision}];
+      int q = mine[0];
+      for (int c : mine)
+        if (load[c] < load[q] || (load[c] == load[q] && c < q)) q = c;
       part_of[t] = q;
-      load[q] += cost(t);
+      if (!whole_classes) load[q] += cost(t);
     }
   }
   parts.clear();
