@@ -1238,28 +1238,32 @@ __global__ __launch_bounds__(n * kQ) void forward_kernel(const TileDev* __restri
 // ============================== sides whose transposes exceed LDS (n = 256)
 // Persistent form of the update: 512 threads run the lines of each phase in
 // Q n/512 rounds (Q = 16 lanes per line and R = n/16 points per lane by
-// default, which needs no register spills; Q = 8, R = n/8 also exists), the
-// two transposes go through this workgroup's own slot of global scratch
-// ([nd][n] complex, the same layout as the LDS buffer), and each workgroup
-// loops over items blockIdx.x, blockIdx.x + gridDim.x, ...  Phase B writes
-// the support columns of its rows back into the slot in place: a thread
-// reads and writes only its own columns (one residue mod Q) of its own row,
-// so no other thread's input is overwritten.
+// default, which needs no register spills; Q = 8, R = n/8 also exists), and
+// each workgroup loops over items blockIdx.x, blockIdx.x + gridDim.x, ...
+// The two transposes ([nd][n] complex values, 321 KB at n = 256 and NA 0.1)
+// do not fit in LDS; they go through this workgroup's own slot of global
+// scratch, or with HALF, rows 0 .. n/2 - 1 through LDS (up to kBigLdsCols
+// support columns, 157 KB: the workgroup then has the CU's LDS to itself,
+// which its registers already impose) and only rows n/2 .. n - 1 through the
+// slot.  Phase B writes the support columns of its rows back in place: a
+// thread reads and writes only its own columns (one residue mod Q) of its
+// own row, so no other thread's input is overwritten.
 constexpr int kBigThreads = 512;
+constexpr int kBigLdsCols = 157;
+
+// Transpose layout (slot and LDS half): blocks of four consecutive rows of
+// one support column, (row / 4, column, row % 4), `cols` columns per block
+// row.  A wave of the row phase then reads and writes 16 columns x 4 rows =
+// 512 contiguous bytes per instruction, and a column lane 4 rows = 32
+// contiguous bytes, instead of 8-byte pieces n * 8 bytes apart.
+template <int cols>
+__device__ __forceinline__ int big_block(int c, int r) {
+  return ((r >> 2) * cols + c) * 4 + (r & 3);
+}
 
 // FUSED (Q = 16): the fused cross-lane steps and the support pruning Z of
 // update_kernel_rounds, with the same lane-sign bookkeeping (par16).
-// Transpose slot layout of update_kernel_big: blocks of four consecutive rows
-// of one support column, (row / 4, column, row % 4).  A wave of the row
-// phase then reads and writes 16 columns x 4 rows = 512 contiguous bytes per
-// instruction, and a column lane 4 rows = 32 contiguous bytes, instead of
-// 8-byte pieces 2 KB apart (each in a cache line of its own).
-template <int n>
-__device__ __forceinline__ size_t big_block(int c, int r) {
-  return ((size_t)(r >> 2) * n + c) * 4 + (r & 3);
-}
-
-template <int n, int Q, bool FUSED = false, int Z = 0>
+template <int n, int Q, bool FUSED = false, int Z = 0, bool HALF = false>
 __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* __restrict__ tiles,
                                                                  const Item* __restrict__ items,
                                                                  int count,
@@ -1272,6 +1276,8 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
   __shared__ float2 tw[n];
   __shared__ float red_pmax[NW];
   __shared__ double red_e[NW], red_i[NW];
+  // rows 0 .. n/2 - 1 of the transposes (HALF); one element otherwise
+  __shared__ float2 lh[HALF ? kBigLdsCols * (n / 2) : 1];
   const int tid0 = threadIdx.x;
   for (int e = tid0; e < n; e += NT) tw[e] = make_float2(kTw<n>.c[e], kTw<n>.s[e]);
   float2* __restrict__ sb = scratch + (size_t)blockIdx.x * n * n;
@@ -1321,12 +1327,25 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           line_dit<n, true, Q>(a, q, tw);
         }
         // rows xc .. xc + R - 1 of support column `line`, four rows at a time
-        float4* dst = reinterpret_cast<float4*>(sb);
+        // (all in the LDS half or all in the slot: R divides n/2)
+        if (HALF && xc < n / 2) {
+          float4* dst = reinterpret_cast<float4*>(lh);
 #pragma unroll
-        for (int j = 0; j < R / 4; ++j) {
-          const size_t b = big_block<n>(line, xc + 4 * j) / 2;
-          dst[b] = make_float4(a[4 * j].x, a[4 * j].y, a[4 * j + 1].x, a[4 * j + 1].y);
-          dst[b + 1] = make_float4(a[4 * j + 2].x, a[4 * j + 2].y, a[4 * j + 3].x, a[4 * j + 3].y);
+          for (int j = 0; j < R / 4; ++j) {
+            const int b = big_block<kBigLdsCols>(line, xc + 4 * j) / 2;
+            dst[b] = make_float4(a[4 * j].x, a[4 * j].y, a[4 * j + 1].x, a[4 * j + 1].y);
+            dst[b + 1] =
+                make_float4(a[4 * j + 2].x, a[4 * j + 2].y, a[4 * j + 3].x, a[4 * j + 3].y);
+          }
+        } else {
+          float4* dst = reinterpret_cast<float4*>(sb);
+#pragma unroll
+          for (int j = 0; j < R / 4; ++j) {
+            const size_t b = (size_t)big_block<n>(line, xc + 4 * j) / 2;
+            dst[b] = make_float4(a[4 * j].x, a[4 * j].y, a[4 * j + 1].x, a[4 * j + 1].y);
+            dst[b + 1] =
+                make_float4(a[4 * j + 2].x, a[4 * j + 2].y, a[4 * j + 3].x, a[4 * j + 3].y);
+          }
         }
       }
     }
@@ -1341,6 +1360,7 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       const int line = l0 + LPR * rd;
       int q = q_item;  // opaque per round: keeps twiddle reads inside the round
       asm volatile("" : "+v"(q));
+      const bool in_lds = HALF && line < n / 2;  // uniform over the round
 #pragma unroll
       for (int p = 0; p < R; ++p) {
         if (p < Z || p >= R - Z) {  // outside every support column
@@ -1348,7 +1368,11 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           continue;
         }
         const int c = q + Q * p - t.kx0;
-        a[p] = (c >= 0 && c < t.nd) ? sb[big_block<n>(c, line)] : make_float2(0.0f, 0.0f);
+        const bool live = c >= 0 && c < t.nd;
+        if (in_lds)
+          a[p] = live ? lh[big_block<kBigLdsCols>(c, line)] : make_float2(0.0f, 0.0f);
+        else
+          a[p] = live ? sb[big_block<n>(c, line)] : make_float2(0.0f, 0.0f);
       }
       if constexpr (FUSED)
         line_dit_f<n, true, 0, Z, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
@@ -1374,7 +1398,12 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       for (int k = 0; k < R; ++k) {
         if (k < Z || k >= R - Z) continue;  // no support column there
         const int c = q + Q * k - t.kx0;
-        if (c >= 0 && c < t.nd) sb[big_block<n>(c, line)] = a[k];
+        if (c >= 0 && c < t.nd) {
+          if (in_lds)
+            lh[big_block<kBigLdsCols>(c, line)] = a[k];
+          else
+            sb[big_block<n>(c, line)] = a[k];
+        }
       }
     }
     {
@@ -1397,11 +1426,20 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       int q = q_item;  // opaque per round: keeps twiddle reads inside the round
       asm volatile("" : "+v"(q));
       if (line < t.nd) {
-        const float4* src = reinterpret_cast<const float4*>(sb);
 #pragma unroll
         for (int j = 0; j < R / 4; ++j) {
-          const size_t b = big_block<n>(line, xc + 4 * j) / 2;
-          const float4 f0 = src[b], f1 = src[b + 1];
+          float4 f0, f1;
+          if (HALF && xc < n / 2) {
+            const float4* src = reinterpret_cast<const float4*>(lh);
+            const int b = big_block<kBigLdsCols>(line, xc + 4 * j) / 2;
+            f0 = src[b];
+            f1 = src[b + 1];
+          } else {
+            const float4* src = reinterpret_cast<const float4*>(sb);
+            const size_t b = (size_t)big_block<n>(line, xc + 4 * j) / 2;
+            f0 = src[b];
+            f1 = src[b + 1];
+          }
           a[4 * j] = make_float2(f0.x, f0.y);
           a[4 * j + 1] = make_float2(f0.z, f0.w);
           a[4 * j + 2] = make_float2(f1.x, f1.y);
@@ -1998,7 +2036,10 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
                          items, count, big_scratch);
     } else {
       const int z = std::min(3, prune_count(256, 16, nd_max));
-      if (z >= 3)
+      if (z >= 3 && nd_max <= kBigLdsCols)
+        hipLaunchKernelGGL((update_kernel_big<256, 16, true, 3, true>), dim3(grid),
+                           dim3(kBigThreads), 0, st, tiles, items, count, big_scratch);
+      else if (z >= 3)
         hipLaunchKernelGGL((update_kernel_big<256, 16, true, 3>), dim3(grid), dim3(kBigThreads), 0,
                            st, tiles, items, count, big_scratch);
       else if (z == 2)
