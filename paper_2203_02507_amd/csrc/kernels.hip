@@ -813,6 +813,43 @@ __device__ __forceinline__ void load_pupil_column(__amdgpu_buffer_rsrc_t Pw, int
   }
 }
 
+// The update of one support pixel from the transformed exit wave av (with
+// the lane sign folded into sig_d, inv_ps and inv_ss), the stored spectrum
+// xs and the pupil pv: the spectrum step and, with pupil recovery, the pupil
+// step or its increment.  offS / offP are kOob outside the pixel's chord.
+template <bool SEQ>
+__device__ __forceinline__ void update_px(float2 av, float2 xs, float2 pv,
+                                          __amdgpu_buffer_rsrc_t Sw, __amdgpu_buffer_rsrc_t Pw,
+                                          __amdgpu_buffer_rsrc_t Dw, int offS, int offP,
+                                          float sig_d, float inv_ps, float inv_ss, bool upd_s,
+                                          int mode, int slot, int count) {
+  // explicit fused multiply-adds: every caller rounds the update identically,
+  // whatever the compiler contracts elsewhere
+  const float2 px = cmul_fma(pv, xs);  // D = Phi' - sigma P X
+  const float2 d = make_float2(fmaf(-px.x, sig_d, av.x), fmaf(-px.y, sig_d, av.y));
+  const float2 ts = cmulc_fma(d, pv);
+  bstore2(Sw, upd_s ? offS : kOob, make_float2(fmaf(ts.x, inv_ps, xs.x), fmaf(ts.y, inv_ps, xs.y)));
+  if (mode != 0) {
+    const float2 tp = cmulc_fma(d, xs);
+    if (mode == 1) {
+      bstore2(Pw, offP, make_float2(fmaf(tp.x, inv_ss, pv.x), fmaf(tp.y, inv_ss, pv.y)));
+    } else {
+      // the increment is rounded before any sum, as when it is stored for
+      // the separate group-mean kernel
+      const float2 dp = make_float2(__fmul_rn(tp.x, inv_ss), __fmul_rn(tp.y, inv_ss));
+      if constexpr (SEQ) {
+        const float2 acc = slot == 0 ? dp : cadd(bload2(Dw, offP), dp);
+        if (slot == count - 1)
+          bstore2(Pw, offP, pupil_mean_step(pv, acc, count));
+        else
+          bstore2(Dw, offP, acc);
+      } else {
+        bstore2(Dw, offP, dp);
+      }
+    }
+  }
+}
+
 template <int n, int Q = kQ, bool SEQ = false, bool PRE = false, int Z = 0>
 __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
                                               __amdgpu_buffer_rsrc_t Sw,
@@ -842,32 +879,8 @@ __device__ __forceinline__ void update_column(const float2 (&a)[n / Q],
     // stored spectrum (this WG's own support pixels), loaded here or ahead
     const float2 xs = PRE ? xs_pre[k] : bload2(Sw, offS);
     const float2 pv = PRE ? pv_pre[k] : bload2(Pw, offP);
-    // explicit fused multiply-adds: every instantiation of this function
-    // rounds the update identically, whatever the compiler contracts elsewhere
-    const float2 px = cmul_fma(pv, xs);  // D = Phi' - sigma P X
-    const float2 d = make_float2(fmaf(-px.x, sig_d, a[k].x), fmaf(-px.y, sig_d, a[k].y));
-    const float2 ts = cmulc_fma(d, pv);
-    bstore2(Sw, upd_s ? offS : kOob,
-            make_float2(fmaf(ts.x, inv_ps, xs.x), fmaf(ts.y, inv_ps, xs.y)));
-    if (mode != 0) {
-      const float2 tp = cmulc_fma(d, xs);
-      if (mode == 1) {
-        bstore2(Pw, offP, make_float2(fmaf(tp.x, inv_ss, pv.x), fmaf(tp.y, inv_ss, pv.y)));
-      } else {
-        // the increment is rounded before any sum, as when it is stored for
-        // the separate group-mean kernel
-        const float2 dp = make_float2(__fmul_rn(tp.x, inv_ss), __fmul_rn(tp.y, inv_ss));
-        if constexpr (SEQ) {
-          const float2 acc = slot == 0 ? dp : cadd(bload2(Dw, offP), dp);
-          if (slot == count - 1)
-            bstore2(Pw, offP, pupil_mean_step(pv, acc, count));
-          else
-            bstore2(Dw, offP, acc);
-        } else {
-          bstore2(Dw, offP, dp);
-        }
-      }
-    }
+    update_px<SEQ>(a[k], xs, pv, Sw, Pw, Dw, offS, offP, sig_d, inv_ps, inv_ss, upd_s, mode, slot,
+                   count);
   }
 }
 
@@ -1061,19 +1074,56 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   lds_barrier();  // twiddles ready
 
   // ---- phase A: support columns, IFFT along ky
+  // Q = 8: sigma P S of every support column is first read row by row (a
+  // wave takes two rows of LPR consecutive columns, whole row segments) into
+  // the column's LDS row at its ky; after one barrier each column's lanes
+  // take their values from there.  Read column by column, every load
+  // instruction of a wave touched eight rows, 64 bytes of each.  Thread
+  // (c_off, y_off) takes the rows y_off + Q p of its columns, the rows lane
+  // q = y_off of a line holds; the input sign of row ky is par8(ky mod 8).
   float pm = 0.0f;
+  const int c_off = tid % LPR, y_off = tid / LPR;  // y_off < Q
+  if constexpr (Q == 8) {
+    const float s0 = sigf / (float)(n * n);
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int c = LPR * rd + c_off;
+      if (c < t.nd) {
+        const int kx = t.kx0 + c;
+        const int2 ch = t.chord[kx];
+        float2 xs[R], pv[R];
+#pragma unroll
+        for (int p = Z; p < R - Z; ++p) {
+          const int ky = y_off + Q * p;
+          const bool in = ky >= ch.x && ky <= ch.y;
+          xs[p] = bload2(Sw, in ? (ky * N + kx) * 8 : kOob);
+          pv[p] = bload2(Pw, in ? (ky * n + kx) * 8 : kOob);
+        }
+        float2* col = sbuf + c * PT;
+#pragma unroll
+        for (int p = Z; p < R - Z; ++p) {
+          const int ky = y_off + Q * p;
+          pm = fmaxf(pm, cabs2(pv[p]));
+          col[ky] = cscale(cmul(pv[p], xs[p]), par8(ky & 7) * s0);
+        }
+      }
+    }
+    lds_barrier();
+  }
 #pragma unroll 1
   for (int rd = 0; rd < ROUNDS; ++rd) {
     const int line = l0 + LPR * rd;
     if (line < t.nd) {
       const int q = R > 16 ? opaque(q_item) : q_item;
-      const int kx = t.kx0 + line;
       if constexpr (Q == 8) {
-        // input signs par8(q) (folded into the gather scale), output signs +1
-        pm = fmaxf(pm, gather_phi<n, Q, Z>(Sw, Pw, N, kx, t.chord[kx], q,
-                                           par8(q) * (sigf / (float)(n * n)), a));
+        // input signs par8(q) (folded into the staged values), output signs +1
+        const float2* col = sbuf + line * PT;
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+          a[p] = (p < Z || p >= R - Z) ? make_float2(0.0f, 0.0f) : col[q + Q * p];
         line_dit_f<n, true, PT, Z>(a, q, tw, -1.0f);
       } else {
+        const int kx = t.kx0 + line;
         pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
         line_dit<n, true, Q, PT>(a, q, tw);
       }
@@ -1141,30 +1191,73 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
 #pragma unroll
   for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
   const float smax = __uint_as_float(*t.smax);  // max |S_stored|^2
+  if constexpr (Q == 8) {
+    // the column FFTs' outputs go back to each column's LDS row at their ky
+    // (a line's lanes read all of the row before any of them writes it: one
+    // wave); after one barrier the update runs row by row over whole row
+    // segments, as the gather does, with the lane sign par8(ky mod 8)
 #pragma unroll 1
-  for (int rd = 0; rd < ROUNDS; ++rd) {
-    const int line = l0 + LPR * rd;
-    if (line < t.nd) {
-      const int q = R > 16 ? opaque(q_item) : q_item;
-      const int kx = t.kx0 + line;
-      const int2 ch = t.chord[kx];
-      // the column's stored spectrum is requested before its transform where
-      // registers allow (R <= 16); longer lane segments load it in the update
-      constexpr bool kPre = R <= 16;
-      float2 xs[kPre ? R : 1], pv[kPre ? R : 1];
-      if constexpr (kPre) {
-        load_column<n, Q, Z>(Sw, N, kx, ch, q, xs);
-        load_pupil_column<n, Q, Z>(Pw, kx, ch, q, pv);
-      }
-      const float2* srcp = sbuf + line * PT + xc;
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      if (line < t.nd) {
+        const int q = q_item;
+        float2* col = sbuf + line * PT;
 #pragma unroll
-      for (int m = 0; m < R; ++m) a[m] = srcp[m];
-      if constexpr (Q == 8) {
-        // output signs par8(q), cancelled inside the update
-        line_dif_f<n, false, PT>(a, q, tw, 1.0f);
-        update_column<n, Q, SEQ, kPre, Z>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
-                                          it.slot, it.gsize, xs, pv, par8(q));
-      } else {
+        for (int m = 0; m < R; ++m) a[m] = col[xc + m];
+        line_dif_f<n, false, PT>(a, q, tw, 1.0f);  // output signs par8(q)
+#pragma unroll
+        for (int k = Z; k < R - Z; ++k) col[q + Q * k] = a[k];
+      }
+    }
+    lds_barrier();
+    const float ips = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
+    const float iss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int c = LPR * rd + c_off;
+      if (c < t.nd) {
+        const int kx = t.kx0 + c;
+        const int2 ch = t.chord[kx];
+        float2 xs[R], pv[R];
+        int offS[R], offP[R];
+#pragma unroll
+        for (int p = Z; p < R - Z; ++p) {
+          const int ky = y_off + Q * p;
+          const bool in = ky >= ch.x && ky <= ch.y;
+          offS[p] = in ? (ky * N + kx) * 8 : kOob;
+          offP[p] = in ? (ky * n + kx) * 8 : kOob;
+          xs[p] = bload2(Sw, offS[p]);
+          pv[p] = bload2(Pw, offP[p]);
+        }
+        const float2* col = sbuf + c * PT;
+#pragma unroll
+        for (int p = Z; p < R - Z; ++p) {
+          const int ky = y_off + Q * p;
+          const float ls = par8(ky & 7);
+          update_px<SEQ>(col[ky], xs[p], pv[p], Sw, Pw, Dw, offS[p], offP[p], ls * sigf, ls * ips,
+                         ls * iss, pmax2 > 0.0f, mode, it.slot, it.gsize);
+        }
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int line = l0 + LPR * rd;
+      if (line < t.nd) {
+        const int q = R > 16 ? opaque(q_item) : q_item;
+        const int kx = t.kx0 + line;
+        const int2 ch = t.chord[kx];
+        // the column's stored spectrum is requested before its transform where
+        // registers allow (R <= 16); longer lane segments load it in the update
+        constexpr bool kPre = R <= 16;
+        float2 xs[kPre ? R : 1], pv[kPre ? R : 1];
+        if constexpr (kPre) {
+          load_column<n, Q, Z>(Sw, N, kx, ch, q, xs);
+          load_pupil_column<n, Q, Z>(Pw, kx, ch, q, pv);
+        }
+        const float2* srcp = sbuf + line * PT + xc;
+#pragma unroll
+        for (int m = 0; m < R; ++m) a[m] = srcp[m];
         line_dif<n, false, Q, PT>(a, q, tw);
         update_column<n, Q, SEQ, kPre>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
                                        it.slot, it.gsize, xs, pv);
@@ -1310,7 +1403,28 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
     float2 a[R];
 
     // ---- phase A: support columns, IFFT along ky, to the scratch slot
+    // (HALF form: each column's stored spectrum and pupil are requested one
+    // round ahead, so that their latency overlaps the previous column's
+    // transform; the LDS half already limits the CU to this workgroup, so the
+    // registers that takes cost no occupancy)
     float pm = 0.0f;
+    float2 gs[HALF ? R : 1], gp[HALF ? R : 1];
+    auto gather_load = [&](int line, int q) {
+      const int kx = t.kx0 + line;
+      const int2 ch = t.chord[kx];
+      const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        if (p < Z || p >= R - Z) continue;  // outside every support row
+        const int ky = q + Q * p;
+        const bool in = ky >= ch.x && ky <= ch.y;
+        gs[p] = bload2(Sw, in ? s0 + p * (Q * 8) * N : kOob);
+        gp[p] = bload2(Pw, in ? p0 + p * (Q * 8 * n) : kOob);
+      }
+    };
+    if constexpr (HALF) {
+      if (l0 < t.nd) gather_load(l0, q_item);
+    }
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
@@ -1318,7 +1432,21 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       asm volatile("" : "+v"(q));
       if (line < t.nd) {
         const int kx = t.kx0 + line;
-        if constexpr (FUSED) {
+        if constexpr (HALF) {
+          // sigma P S on the column (gather_phi's arithmetic on the requested values)
+          const float scale = par16(q) * (sigf / (float)(n * n));
+#pragma unroll
+          for (int p = 0; p < R; ++p) {
+            if (p < Z || p >= R - Z) {
+              a[p] = make_float2(0.0f, 0.0f);
+              continue;
+            }
+            pm = fmaxf(pm, cabs2(gp[p]));
+            a[p] = cscale(cmul(gp[p], gs[p]), scale);
+          }
+          if (rd + 1 < ROUNDS && line + LPR < t.nd) gather_load(line + LPR, q);
+          line_dit_f<n, true, 0, Z, Q>(a, q, tw, -1.0f);
+        } else if constexpr (FUSED) {
           pm = fmaxf(pm, gather_phi<n, Q, Z>(Sw, Pw, N, kx, t.chord[kx], q,
                                              par16(q) * (sigf / (float)(n * n)), a));
           line_dit_f<n, true, 0, Z, Q>(a, q, tw, -1.0f);
@@ -1354,7 +1482,22 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
     __syncthreads();
 
     // ---- phase B: rows, IFFT along kx, modulus, FFT along x
+    // (HALF form: a row held in the global slot is requested one round
+    // ahead; rows are disjoint between rounds, so the request never reads a
+    // value the current round still writes)
     float e_acc = 0.0f, i_acc = 0.0f;
+    float2 nx[HALF ? R : 1];
+    auto slot_row = [&](int row, int q, float2(&dst)[HALF ? R : 1]) {
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        if (p < Z || p >= R - Z) continue;  // outside every support column
+        const int c = q + Q * p - t.kx0;
+        dst[p] = (c >= 0 && c < t.nd) ? sb[big_block<n>(c, row)] : make_float2(0.0f, 0.0f);
+      }
+    };
+    if constexpr (HALF) {
+      if (l0 >= n / 2) slot_row(l0, q_item, nx);
+    }
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
@@ -1371,8 +1514,14 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
         const bool live = c >= 0 && c < t.nd;
         if (in_lds)
           a[p] = live ? lh[big_block<kBigLdsCols>(c, line)] : make_float2(0.0f, 0.0f);
+        else if constexpr (HALF)
+          a[p] = nx[p];
         else
           a[p] = live ? sb[big_block<n>(c, line)] : make_float2(0.0f, 0.0f);
+      }
+      if constexpr (HALF) {
+        const int next = line + LPR;
+        if (rd + 1 < ROUNDS && next >= n / 2) slot_row(next, q, nx);
       }
       if constexpr (FUSED)
         line_dit_f<n, true, 0, Z, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
