@@ -1403,19 +1403,51 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
     float2 a[R];
 
     // ---- phase A: support columns, IFFT along ky, to the scratch slot
-    // (HALF form: each column's stored spectrum and pupil are requested one
-    // round ahead, so that their latency overlaps the previous column's
-    // transform; the LDS half already limits the CU to this workgroup, so the
-    // registers that takes cost no occupancy)
+    // HALF form: sigma P S of rows 0 .. n/2 - 1 of every support column is
+    // first read row by row (a wave takes four rows of LPR consecutive
+    // columns: whole row segments instead of 32-byte pieces of sixteen rows)
+    // into the LDS half at the column's ky; thread (c_off, y_off) takes the
+    // rows y_off + Q p, those lane q = y_off of a line holds, and the input
+    // sign of row ky is par16(ky mod 16).  Rows n/2 .. n - 1 are read by the
+    // column's lanes, one round ahead, so that their latency overlaps the
+    // previous column's transform (the LDS half already limits the CU to
+    // this workgroup, so the registers that takes cost no occupancy).
     float pm = 0.0f;
+    constexpr int RH = R / 2;  // values q + Q p with p < RH lie in rows 0 .. n/2 - 1
+    const int c_off = tid0 % LPR, y_off = tid0 / LPR;  // y_off < Q
+    if constexpr (HALF) {
+      const float s0 = sigf / (float)(n * n);
+#pragma unroll 1
+      for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int c = LPR * rd + c_off;
+        if (c < t.nd) {
+          const int kx = t.kx0 + c;
+          const int2 ch = t.chord[kx];
+          float2 xs[RH], pv[RH];
+#pragma unroll
+          for (int p = Z; p < RH; ++p) {
+            const int ky = y_off + Q * p;
+            const bool in = ky >= ch.x && ky <= ch.y;
+            xs[p] = bload2(Sw, in ? (ky * N + kx) * 8 : kOob);
+            pv[p] = bload2(Pw, in ? (ky * n + kx) * 8 : kOob);
+          }
+#pragma unroll
+          for (int p = Z; p < RH; ++p) {
+            const int ky = y_off + Q * p;
+            pm = fmaxf(pm, cabs2(pv[p]));
+            lh[big_block<kBigLdsCols>(c, ky)] = cscale(cmul(pv[p], xs[p]), par16(ky & 15) * s0);
+          }
+        }
+      }
+      __syncthreads();
+    }
     float2 gs[HALF ? R : 1], gp[HALF ? R : 1];
     auto gather_load = [&](int line, int q) {
       const int kx = t.kx0 + line;
       const int2 ch = t.chord[kx];
       const int s0 = (q * N + kx) * 8, p0 = (q * n + kx) * 8;
 #pragma unroll
-      for (int p = 0; p < R; ++p) {
-        if (p < Z || p >= R - Z) continue;  // outside every support row
+      for (int p = RH; p < R - Z; ++p) {
         const int ky = q + Q * p;
         const bool in = ky >= ch.x && ky <= ch.y;
         gs[p] = bload2(Sw, in ? s0 + p * (Q * 8) * N : kOob);
@@ -1433,16 +1465,21 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
       if (line < t.nd) {
         const int kx = t.kx0 + line;
         if constexpr (HALF) {
-          // sigma P S on the column (gather_phi's arithmetic on the requested values)
+          // sigma P S on the column: the staged values, and gather_phi's
+          // arithmetic on the requested ones (each lane reads its line's LDS
+          // values before any lane of the line, in the same wave, writes
+          // the line's transform over them)
           const float scale = par16(q) * (sigf / (float)(n * n));
 #pragma unroll
           for (int p = 0; p < R; ++p) {
             if (p < Z || p >= R - Z) {
               a[p] = make_float2(0.0f, 0.0f);
-              continue;
+            } else if (p < RH) {
+              a[p] = lh[big_block<kBigLdsCols>(line, q + Q * p)];
+            } else {
+              pm = fmaxf(pm, cabs2(gp[p]));
+              a[p] = cscale(cmul(gp[p], gs[p]), scale);
             }
-            pm = fmaxf(pm, cabs2(gp[p]));
-            a[p] = cscale(cmul(gp[p], gs[p]), scale);
           }
           if (rd + 1 < ROUNDS && line + LPR < t.nd) gather_load(line + LPR, q);
           line_dit_f<n, true, 0, Z, Q>(a, q, tw, -1.0f);
@@ -1569,6 +1606,8 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 #pragma unroll
     for (int w = 1; w < NW; ++w) pmax2 = fmaxf(pmax2, red_pmax[w]);
     const float smax = __uint_as_float(*t.smax);
+    const float ips = pmax2 > 0.0f ? 1.0f / (pmax2 * sigf) : 0.0f;
+    const float iss = smax > 0.0f ? 1.0f / (smax * sigf) : 0.0f;
 #pragma unroll 1
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int line = l0 + LPR * rd;
@@ -1595,13 +1634,61 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
           a[4 * j + 3] = make_float2(f1.z, f1.w);
         }
         const int kx = t.kx0 + line;
-        if constexpr (FUSED) {
+        if constexpr (HALF) {
+          // rows n/2 .. n - 1 updated here, column by column; rows 0 .. n/2 - 1
+          // go back to the LDS half for the row-segment update below
+          line_dif_f<n, false, 0, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
+#pragma unroll
+          for (int k = Z; k < RH; ++k) lh[big_block<kBigLdsCols>(line, q + Q * k)] = a[k];
+          const int2 ch = t.chord[kx];
+          const float ls = par16(q);
+#pragma unroll
+          for (int k = RH; k < R - Z; ++k) {
+            const int ky = q + Q * k;
+            const bool in = ky >= ch.x && ky <= ch.y;
+            const int offS = in ? (ky * N + kx) * 8 : kOob;
+            const int offP = in ? (ky * n + kx) * 8 : kOob;
+            update_px<false>(a[k], bload2(Sw, offS), bload2(Pw, offP), Sw, Pw, Dw, offS, offP,
+                             ls * sigf, ls * ips, ls * iss, pmax2 > 0.0f, t.mode, 0, 1);
+          }
+        } else if constexpr (FUSED) {
           line_dif_f<n, false, 0, Q>(a, q, tw, 1.0f);  // lane signs par16(q)
           update_column<n, Q, false, false, Z>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2,
                                                smax, t.mode, 0, 1, nullptr, nullptr, par16(q));
         } else {
           line_dif<n, false, Q>(a, q, tw);
           update_column<n, Q>(a, Sw, Pw, Dw, N, kx, t.chord[kx], q, sigf, pmax2, smax, t.mode);
+        }
+      }
+    }
+    if constexpr (HALF) {
+      // the update of rows 0 .. n/2 - 1 by whole row segments, the pixels each
+      // thread staged in phase A (lane sign par16(ky mod 16) of each value)
+      __syncthreads();
+#pragma unroll 1
+      for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int c = LPR * rd + c_off;
+        if (c < t.nd) {
+          const int kx = t.kx0 + c;
+          const int2 ch = t.chord[kx];
+          float2 xs[RH], pv[RH];
+          int offS[RH], offP[RH];
+#pragma unroll
+          for (int p = Z; p < RH; ++p) {
+            const int ky = y_off + Q * p;
+            const bool in = ky >= ch.x && ky <= ch.y;
+            offS[p] = in ? (ky * N + kx) * 8 : kOob;
+            offP[p] = in ? (ky * n + kx) * 8 : kOob;
+            xs[p] = bload2(Sw, offS[p]);
+            pv[p] = bload2(Pw, offP[p]);
+          }
+#pragma unroll
+          for (int p = Z; p < RH; ++p) {
+            const int ky = y_off + Q * p;
+            const float ls = par16(ky & 15);
+            update_px<false>(lh[big_block<kBigLdsCols>(c, ky)], xs[p], pv[p], Sw, Pw, Dw, offS[p],
+                             offP[p], ls * sigf, ls * ips, ls * iss, pmax2 > 0.0f, t.mode, 0, 1);
+          }
         }
       }
     }
