@@ -779,6 +779,10 @@ def main():
                          "kernel": f"mfma_update_kernel<{tds[0].desc.n}>",
                          "mfma_flops_per_update": issued,
                          "dense_dft_flops_per_update": dense,
+                         # the same run time priced on the unpadded support's
+                         # dense DFT products (no tile padding, no zero rows)
+                         "frac_dense": round(dense * upd["items"] / (upd["busy_ms"] / 1e3)
+                                             / 1e12 / MFMA_PEAK_TFLOPS, 4),
                          "updates_per_launch": round(per_launch, 1),
                          "busy_ms": round(upd["busy_ms"], 3),
                          "mean_launch_us": round(mean_s * 1e6, 2)},
