@@ -140,3 +140,30 @@ def test_n256_fused_form_bitwise(fpm, orc, monkeypatch):
         o_ref, _, r_ref = oracle_run(orc, d, Is[t])
         assert rel(outs["7"][t][0], o_ref) <= TOL_OBJ, t
         assert np.allclose(outs["7"][t][2], r_ref, rtol=1e-4, atol=1e-9), t
+
+
+def test_n256_wide_support_bitwise(fpm, orc, monkeypatch):
+    """A support wider than the LDS half holds (NA 0.13: 203 support
+    columns > 157) runs the fused form with both transposes in the global
+    slot and a smaller pruning; its bits are still those of the unfused
+    16-lane form, and it matches the oracle.  Mixed in one launch with an
+    NA 0.1 tile, whose launch then takes the same wide path."""
+    tds = [tile256(51, na_obj=0.13, upsample=4, schedule=1, pupil_update=1),
+           tile256(52, schedule=0, pupil_update=1)]
+    descs, Is = [], []
+    for td in tds:
+        _, _, I = orc.synthesize(td)
+        descs.append(td.desc)
+        Is.append(I)
+    outs = {}
+    for v in ("2", "7"):
+        monkeypatch.setenv("FPM_UPDATE_VARIANT_256", v)
+        print(f"variant {v}", flush=True)
+        outs[v] = run_gpu(fpm, descs, Is)
+    for a, b in zip(outs["2"], outs["7"]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    o_ref, _, r_ref = oracle_run(orc, descs[0], Is[0])
+    err = rel(outs["7"][0][0], o_ref)
+    print(f"NA 0.13 tile: rel L2 {err:.3e}")
+    assert err <= TOL_OBJ
+    assert np.allclose(outs["7"][0][2], r_ref, rtol=1e-4, atol=1e-9)
