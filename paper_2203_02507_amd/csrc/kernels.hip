@@ -1404,7 +1404,7 @@ __global__ __launch_bounds__(kBigThreads) void update_kernel_big(const TileDev* 
 
     // ---- phase A: support columns, IFFT along ky, to the scratch slot
     // HALF form: sigma P S of rows 0 .. n/2 - 1 of every support column is
-    // first read row by row (a wave takes four rows of LPR consecutive
+    // first read row by row (a wave takes two rows of LPR consecutive
     // columns: whole row segments instead of 32-byte pieces of sixteen rows)
     // into the LDS half at the column's ky; thread (c_off, y_off) takes the
     // rows y_off + Q p, those lane q = y_off of a line holds, and the input
