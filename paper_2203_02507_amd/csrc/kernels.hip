@@ -1050,6 +1050,12 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   static_assert(R % 4 == 0, "intensities are read four at a time");
   extern __shared__ float2 sbuf[];  // [max(nd, n/2)][PT]; column n: twiddles
   float2* const tw = sbuf + n;
+  // Q = 8: position pos (< n) of a row sits at pos ^ (2 ((pos / 16) mod 8)),
+  // a permutation within each aligned block of 16 that keeps pairs
+  // together.  The lanes of a line read and write runs xc .. xc + R - 1
+  // with xc = 16 brev(q): unswizzled, all eight of them start in the same
+  // LDS bank; swizzled, the eight runs start in eight different banks.
+  auto sw = [](int pos) { return Q == 8 ? pos ^ ((pos >> 3) & 14) : pos; };
   __shared__ float red_pmax[NW];
   // residual partials per (round, wave): the waves of update_kernel, in order
   __shared__ double red_e[ROUNDS * NW], red_i[ROUNDS * NW];
@@ -1104,7 +1110,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         for (int p = Z; p < R - Z; ++p) {
           const int ky = y_off + Q * p;
           pm = fmaxf(pm, cabs2(pv[p]));
-          col[ky] = cscale(cmul(pv[p], xs[p]), par8(ky & 7) * s0);
+          col[sw(ky)] = cscale(cmul(pv[p], xs[p]), par8(ky & 7) * s0);
         }
       }
     }
@@ -1120,16 +1126,16 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         const float2* col = sbuf + line * PT;
 #pragma unroll
         for (int p = 0; p < R; ++p)
-          a[p] = (p < Z || p >= R - Z) ? make_float2(0.0f, 0.0f) : col[q + Q * p];
+          a[p] = (p < Z || p >= R - Z) ? make_float2(0.0f, 0.0f) : col[sw(q + Q * p)];
         line_dit_f<n, true, PT, Z>(a, q, tw, -1.0f);
       } else {
         const int kx = t.kx0 + line;
         pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
         line_dit<n, true, Q, PT>(a, q, tw);
       }
-      float2* dst = sbuf + line * PT + xc;
+      float2* dst = sbuf + line * PT;
 #pragma unroll
-      for (int k = 0; k < R; ++k) dst[k] = a[k];
+      for (int k = 0; k < R; ++k) dst[sw(xc + k)] = a[k];
     }
   }
   pm = wave_max(pm);
@@ -1156,7 +1162,15 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
       }
     };
     if constexpr (R <= 16) load_iv(line);
-    load_rows<n, PAD, Q, Z>(sbuf, t.kx0, t.nd, line, q, a);
+#pragma unroll
+    for (int p = 0; p < R; ++p) {  // load_rows, through the swizzle
+      if (p < Z || p >= R - Z) {
+        a[p] = make_float2(0.0f, 0.0f);
+        continue;
+      }
+      const int c = q + Q * p - t.kx0;
+      a[p] = (c >= 0 && c < t.nd) ? sbuf[c * PT + sw(line)] : make_float2(0.0f, 0.0f);
+    }
     // Q = 8: the row IFFT leaves lane signs par8(q), which the modulus keeps
     // and the row FFT removes
     if constexpr (Q == 8)
@@ -1181,7 +1195,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
     for (int k = 0; k < R; ++k) {
       if (k < Z || k >= R - Z) continue;  // no support column there
       const int c = q + Q * k - t.kx0;
-      if (c >= 0 && c < t.nd) sbuf[c * PT + line] = a[k];
+      if (c >= 0 && c < t.nd) sbuf[c * PT + sw(line)] = a[k];
     }
   }
   lds_barrier();
@@ -1203,10 +1217,10 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         const int q = q_item;
         float2* col = sbuf + line * PT;
 #pragma unroll
-        for (int m = 0; m < R; ++m) a[m] = col[xc + m];
+        for (int m = 0; m < R; ++m) a[m] = col[sw(xc + m)];
         line_dif_f<n, false, PT>(a, q, tw, 1.0f);  // output signs par8(q)
 #pragma unroll
-        for (int k = Z; k < R - Z; ++k) col[q + Q * k] = a[k];
+        for (int k = Z; k < R - Z; ++k) col[sw(q + Q * k)] = a[k];
       }
     }
     lds_barrier();
@@ -1234,7 +1248,7 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         for (int p = Z; p < R - Z; ++p) {
           const int ky = y_off + Q * p;
           const float ls = par8(ky & 7);
-          update_px<SEQ>(col[ky], xs[p], pv[p], Sw, Pw, Dw, offS[p], offP[p], ls * sigf, ls * ips,
+          update_px<SEQ>(col[sw(ky)], xs[p], pv[p], Sw, Pw, Dw, offS[p], offP[p], ls * sigf, ls * ips,
                          ls * iss, pmax2 > 0.0f, mode, it.slot, it.gsize);
         }
       }
@@ -1255,9 +1269,9 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
           load_column<n, Q, Z>(Sw, N, kx, ch, q, xs);
           load_pupil_column<n, Q, Z>(Pw, kx, ch, q, pv);
         }
-        const float2* srcp = sbuf + line * PT + xc;
+        const float2* srcp = sbuf + line * PT;
 #pragma unroll
-        for (int m = 0; m < R; ++m) a[m] = srcp[m];
+        for (int m = 0; m < R; ++m) a[m] = srcp[sw(xc + m)];
         line_dif<n, false, Q, PT>(a, q, tw);
         update_column<n, Q, SEQ, kPre>(a, Sw, Pw, Dw, N, kx, ch, q, sigf, pmax2, smax, mode,
                                        it.slot, it.gsize, xs, pv);
