@@ -750,6 +750,30 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
 template <int R>
 __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[R], int line,
                                             int xc, float& e_acc, float& i_acc, int zpar = 0) {
+  // Where no value of the wave's rows is zero or below 2^-100 in |psi|^2
+  // (everywhere but the windows a sweep has not reached yet), the scaling
+  // and zero-field selects below are the identity; that case takes the
+  // same operations without them, one branch for the wave.
+  float p2v[R];
+  bool plain = true;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    p2v[k] = cabs2(a[k]);
+    plain &= p2v[k] >= 0x1p-100f;
+  }
+  if (__all(plain)) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const float I = ipre[k];
+      const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+      const float rinv = __builtin_amdgcn_rsqf(p2v[k]);
+      const float d = p2v[k] * rinv - m;
+      e_acc = fmaf(d, d, e_acc);
+      i_acc += I;
+      a[k] = cscale(a[k], m * rinv);
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
@@ -761,7 +785,7 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
     // frame differs from it by (-1)^(x+y), so the zero-field value is
     // (-1)^(x+y) sqrt(I) here.
     const float m_zero = ((line + xc + k + zpar) & 1) ? -m : m;
-    const float p2 = cabs2(a[k]);
+    const float p2 = p2v[k];
     const bool small = p2 < 0x1p-100f;
     const float2 as = small ? cscale(a[k], 0x1p100f) : a[k];
     const float p2s = small ? cabs2(as) : p2;
