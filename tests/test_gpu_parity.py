@@ -406,3 +406,35 @@ def test_device_mode_errors_write_no_output(fpm, orc):
     o_ref, _, r_ref = oracle_run(orc, td.desc, I)
     assert rel(out[0][0], o_ref) <= TOL_OBJ
     assert fpm.fpm_plan_status(plan2) == fpm.FPM_OK
+
+
+@pytest.mark.parametrize("na", [0.05, 0.15])
+def test_support_widths_bitwise_across_variants(fpm, orc, monkeypatch, na):
+    """Narrow and wide supports (NA 0.05 / 0.15: pruning Z = 5 / 0 at n = 128,
+    Z = 3 / 0 at n = 96) through the round form's row-segment gather and
+    update and its swizzled LDS rows: the four-round variant gives the bits
+    of the one-round 8-lane variant, and both match the oracle."""
+    rng = np.random.default_rng(int(na * 1000))
+    descs, Is = [], []
+    for n, up in ((128, 2), (96, 3)):
+        d = fpm_synth.TileDesc(n=n, upsample=up, led_rows=7, led_cols=7, iterations=2, schedule=1,
+                               pupil_update=1, na_obj=na, tile_x_um=float(rng.uniform(-600, 600)),
+                               tile_y_um=float(rng.uniform(-600, 600)),
+                               defocus_um=float(rng.uniform(-10, 10)))
+        _, _, I = orc.synthesize(fpm_synth.TileDraw(desc=d, rng=rng))
+        descs.append(d)
+        Is.append(I)
+    outs = {}
+    for v in ("4", "7"):
+        monkeypatch.setenv("FPM_UPDATE_VARIANT", v)
+        print(f"NA {na} variant {v}", flush=True)
+        _, outs[v] = run_gpu(fpm, descs, Is)
+    for a, b in zip(outs["4"], outs["7"]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for t, d in enumerate(descs):
+        o_ref, _, r_ref = oracle_run(orc, d, Is[t])
+        o, _, r = outs["7"][t]
+        print(f"n {d.n} NA {na}: rel L2 {rel(o, o_ref):.3e}")
+        assert rel(o, o_ref) <= TOL_OBJ, t
+        check_windows(orc, d, Is[t], o, o_ref, TOL_WIN, f"n {d.n} NA {na}")
+        assert np.allclose(r, r_ref, rtol=1e-4, atol=1e-9), t
