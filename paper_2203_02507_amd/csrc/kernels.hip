@@ -633,6 +633,36 @@ __device__ __forceinline__ void line_dif_f(float2 (&a)[n / Q], int ql, const flo
   fft_reg<R, INV>(a);
 }
 
+// The same two transforms with the line's twiddles W^(ql k), k < R, held in
+// registers (twl[k] in the inverse orientation exp(+2 pi i ql k / n), the
+// forward one taken as its conjugate): a thread keeps its lane ql for the
+// whole kernel, so it reads its R - 1 twiddles once instead of once per
+// line.  The values, and so the results, are bitwise those of the LDS forms.
+template <int n, bool INV, int Z = 0, int Q = 8>
+__device__ __forceinline__ void line_dit_fr(float2 (&a)[n / Q], int ql, const float2 (&twl)[n / Q],
+                                            const float2* tw, float flip) {
+  constexpr int R = n / Q;
+  fft_reg<R, INV, Z, Z>(a);
+#pragma unroll
+  for (int k = 1; k < R; ++k) a[k] = cmul(a[k], INV ? twl[k] : make_float2(twl[k].x, -twl[k].y));
+  if constexpr (Q == 8)
+    xlane8_nat2brev_f<INV>(a, ql, flip);
+  else
+    xlane16_nat2brev_f<n, INV, R, 0>(a, ql, tw, flip);
+}
+template <int n, bool INV, int Q = 8>
+__device__ __forceinline__ void line_dif_fr(float2 (&a)[n / Q], int ql, const float2 (&twl)[n / Q],
+                                            const float2* tw, float flip) {
+  constexpr int R = n / Q;
+  if constexpr (Q == 8)
+    xlane8_brev2nat_f<INV>(a, ql, flip);
+  else
+    xlane16_brev2nat_f<n, INV, R, 0>(a, ql, tw, flip);
+#pragma unroll
+  for (int m = 1; m < R; ++m) a[m] = cmul(a[m], INV ? twl[m] : make_float2(twl[m].x, -twl[m].y));
+  fft_reg<R, INV>(a);
+}
+
 // P + acc / count with one fused multiply-add per component (the group
 // mean, written the same way wherever it is applied)
 __device__ __forceinline__ float2 pupil_mean_step(float2 p, float2 acc, int count) {
@@ -743,6 +773,14 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
   }
 }
 
+// max(I, 0) as one integer maximum: a float with its sign bit clear compares
+// as a non-negative integer in the order of its value, every other one
+// (negative values and -0) gives +0.  The result is fmaxf(I, 0) for every
+// input but NaN, which the entry points reject before any kernel runs.
+__device__ __forceinline__ float clamp0(float I) {
+  return __int_as_float(max(__float_as_int(I), 0));
+}
+
 // Modulus projection of one row segment and its residual partials.
 // a[k] holds psi at (row `line`, column xc + k) of the unshifted frame.
 // zpar = 1: the lane's values carry the sign -1 (fused cross-lane steps);
@@ -765,7 +803,7 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const float I = ipre[k];
-      const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+      const float m = __builtin_amdgcn_sqrtf(clamp0(I));
       const float rinv = __builtin_amdgcn_rsqf(p2v[k]);
       const float d = p2v[k] * rinv - m;
       e_acc = fmaf(d, d, e_acc);
@@ -777,7 +815,7 @@ __device__ __forceinline__ void modulus_row(float2 (&a)[R], const float (&ipre)[
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const float I = ipre[k];
-    const float m = __builtin_amdgcn_sqrtf(fmaxf(I, 0.0f));
+    const float m = __builtin_amdgcn_sqrtf(clamp0(I));
     // psi' = m psi / |psi| through the hardware reciprocal square root, which
     // flushes denormal inputs: a field whose |psi|^2 is below 2^-100 is
     // first scaled by 2^100 (exact), so every nonzero psi keeps its phase.
@@ -1102,6 +1140,14 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
   const float sigf = (float)*t.sigma;
   float2 a[R];
   lds_barrier();  // twiddles ready
+  // Q = 8 with R <= 16: the thread's line twiddles live in registers
+  constexpr bool kTwReg = Q == 8 && R <= 16;
+  float2 twl[R];
+  if constexpr (kTwReg) {
+    twl[0] = make_float2(1.0f, 0.0f);
+#pragma unroll
+    for (int k = 1; k < R; ++k) twl[k] = tw_at<true, n, PT>(tw, q_item * k);
+  }
 
   // ---- phase A: support columns, IFFT along ky
   // Q = 8: sigma P S of every support column is first read row by row (a
@@ -1151,7 +1197,10 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
 #pragma unroll
         for (int p = 0; p < R; ++p)
           a[p] = (p < Z || p >= R - Z) ? make_float2(0.0f, 0.0f) : col[sw(q + Q * p)];
-        line_dit_f<n, true, PT, Z>(a, q, tw, -1.0f);
+        if constexpr (kTwReg)
+          line_dit_fr<n, true, Z>(a, q, twl, tw, -1.0f);
+        else
+          line_dit_f<n, true, PT, Z>(a, q, tw, -1.0f);
       } else {
         const int kx = t.kx0 + line;
         pm = fmaxf(pm, gather_phi<n, Q>(Sw, Pw, N, kx, t.chord[kx], q, sigf / (float)(n * n), a));
@@ -1197,7 +1246,9 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
     }
     // Q = 8: the row IFFT leaves lane signs par8(q), which the modulus keeps
     // and the row FFT removes
-    if constexpr (Q == 8)
+    if constexpr (kTwReg)
+      line_dit_fr<n, true, Z>(a, q, twl, tw, 1.0f);
+    else if constexpr (Q == 8)
       line_dit_f<n, true, PT, Z>(a, q, tw, 1.0f);
     else
       line_dit<n, true, Q, PT>(a, q, tw);
@@ -1211,7 +1262,9 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         red_i[rd * NW + wave] = s2;
       }
     }
-    if constexpr (Q == 8)
+    if constexpr (kTwReg)
+      line_dif_fr<n, false>(a, q, twl, tw, -1.0f);
+    else if constexpr (Q == 8)
       line_dif_f<n, false, PT>(a, q, tw, -1.0f);
     else
       line_dif<n, false, Q, PT>(a, q, tw);
@@ -1242,7 +1295,10 @@ __global__ __launch_bounds__(n * Q / ROUNDS, 2 * (n * Q / ROUNDS) / 256) void up
         float2* col = sbuf + line * PT;
 #pragma unroll
         for (int m = 0; m < R; ++m) a[m] = col[sw(xc + m)];
-        line_dif_f<n, false, PT>(a, q, tw, 1.0f);  // output signs par8(q)
+        if constexpr (kTwReg)
+          line_dif_fr<n, false>(a, q, twl, tw, 1.0f);  // output signs par8(q)
+        else
+          line_dif_f<n, false, PT>(a, q, tw, 1.0f);
 #pragma unroll
         for (int k = Z; k < R - Z; ++k) col[sw(q + Q * k)] = a[k];
       }
