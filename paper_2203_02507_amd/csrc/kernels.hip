@@ -773,6 +773,9 @@ __device__ __forceinline__ void load_rows(const float2* buf, int kx0, int nd, in
   }
 }
 
+// threads of the iteration-end kernel (one workgroup per tile)
+constexpr int kIterEndThreads = 1024;
+
 // max(I, 0) as one integer maximum: a float with its sign bit clear compares
 // as a non-negative integer in the order of its value, every other one
 // (negative values and -0) gives +0.  The result is fmaxf(I, 0) for every
@@ -1882,21 +1885,25 @@ __global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __rest
 // residual = sum_j e_j / sum_j I_j (LEDs in grid order); with pupil
 // recovery: s = sqrt(|D0| / sum_D0 |P|^2), P <- s P, sigma <- sigma / s.
 // Also clears the running spectrum maximum for the next iteration.
-__global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict__ tiles,
-                                                       const int* __restrict__ ids, int iter) {
+__global__ __launch_bounds__(kIterEndThreads) void iter_end_kernel(const TileDev* __restrict__ tiles,
+                                                                   const int* __restrict__ ids,
+                                                                   int iter) {
   const TileDev t = tiles[ids[blockIdx.x]];
   const int pupil_update = t.mode != 0;
   const int tid = threadIdx.x;
-  __shared__ double r0[256], r1[256];
+  __shared__ double r0[kIterEndThreads], r1[256];
   __shared__ double s_scale;
-  double e = 0.0, s = 0.0;
-  const size_t e0 = (size_t)iter * t.e_stride;
-  for (int j = tid; j < t.L; j += 256) {
-    e += t.e_part[e0 + j];
-    s += t.i_part[e0 + j];
+  // residual: the first 256 threads sum the per-LED partials
+  if (tid < 256) {
+    double e = 0.0, s = 0.0;
+    const size_t e0 = (size_t)iter * t.e_stride;
+    for (int j = tid; j < t.L; j += 256) {
+      e += t.e_part[e0 + j];
+      s += t.i_part[e0 + j];
+    }
+    r0[tid] = e;
+    r1[tid] = s;
   }
-  r0[tid] = e;
-  r1[tid] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) {
@@ -1908,19 +1915,23 @@ __global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict
   if (tid == 0) t.residual[iter] = r1[0] > 0.0 ? r0[0] / r1[0] : 0.0;
   __syncthreads();
   if (pupil_update) {
-    const int n = t.n;
+    // thread (kx, y0) takes column kx, rows y0, y0 + per, ... (one chord
+    // lookup per thread)
+    const int n = t.n, per = kIterEndThreads / n;
+    const int kx = tid % n, y0 = tid / n;
     double E = 0.0;
-    for (int px = tid; px < n * n; px += 256) {
-      const int ky = px / n, kx = px % n;
+    if (y0 < per) {
       const int2 ch = t.chord[kx];
-      if (ky >= ch.x && ky <= ch.y) {
-        const float2 p = t.P[px];
-        E += (double)p.x * (double)p.x + (double)p.y * (double)p.y;
+      for (int ky = y0; ky < n; ky += per) {
+        if (ky >= ch.x && ky <= ch.y) {
+          const float2 p = t.P[ky * n + kx];
+          E += (double)p.x * (double)p.x + (double)p.y * (double)p.y;
+        }
       }
     }
     r0[tid] = E;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = kIterEndThreads / 2; o > 0; o >>= 1) {
       if (tid < o) r0[tid] += r0[tid + o];
       __syncthreads();
     }
@@ -1931,7 +1942,8 @@ __global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict
     }
     __syncthreads();
     const float sc = (float)s_scale;
-    for (int px = tid; px < n * n; px += 256) t.P[px] = cscale(t.P[px], sc);
+    if (y0 < per)
+      for (int ky = y0; ky < n; ky += per) t.P[ky * n + kx] = cscale(t.P[ky * n + kx], sc);
   }
   if (tid == 0) *t.smax = 0u;
 }
@@ -1941,10 +1953,16 @@ __global__ __launch_bounds__(256) void iter_end_kernel(const TileDev* __restrict
 __global__ __launch_bounds__(256) void smax_kernel(const TileDev* __restrict__ tiles,
                                                    const int* __restrict__ ids) {
   const TileDev t = tiles[ids[blockIdx.y]];
-  const size_t NN = (size_t)t.N * t.N;
+  // two complex values per 16-byte load (S is 256-byte aligned)
+  const size_t NN2 = (size_t)t.N * t.N / 2;
+  const float4* S4 = reinterpret_cast<const float4*>(t.S);
   float m = 0.0f;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN; i += (size_t)gridDim.x * 256)
-    m = fmaxf(m, cabs2(t.S[i]));
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < NN2; i += (size_t)gridDim.x * 256) {
+    const float4 v = S4[i];
+    m = fmaxf(m, fmaxf(fmaf(v.x, v.x, v.y * v.y), fmaf(v.z, v.z, v.w * v.w)));
+  }
+  if ((t.N & 1) && blockIdx.x == 0 && threadIdx.x == 0)  // odd N: the last value
+    m = fmaxf(m, cabs2(t.S[(size_t)t.N * t.N - 1]));
   m = wave_max(m);
   __shared__ float wm[4];
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
@@ -2423,14 +2441,14 @@ hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int 
 hipError_t launch_iter_end(const TileDev* tiles, const int* ids, int count, int iter,
                            hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(iter_end_kernel, dim3(count), dim3(256), 0, st, tiles, ids, iter);
+  hipLaunchKernelGGL(iter_end_kernel, dim3(count), dim3(kIterEndThreads), 0, st, tiles, ids, iter);
   return hipGetLastError();
 }
 
 hipError_t launch_smax(const TileDev* tiles, const int* ids, int count, int NN_max,
                        hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  const int chunks = (NN_max + 256 * 16 - 1) / (256 * 16);
+  const int chunks = (NN_max / 2 + 256 * 16 - 1) / (256 * 16);
   hipLaunchKernelGGL(smax_kernel, dim3(chunks, count), dim3(256), 0, st, tiles, ids);
   return hipGetLastError();
 }
