@@ -2036,25 +2036,28 @@ __global__ __launch_bounds__(256) void line_fft_kernel(const LineJob* __restrict
   extern __shared__ float2 lbuf[];
   float2* x = lbuf;
   float2* y = lbuf + len;
+  float2* w = lbuf + 2 * len;  // w[e] = W_len^e, in FP64 and rounded once
   float2* base = job.base + (size_t)line * job.line_stride;
-  for (int i = threadIdx.x; i < len; i += 256) x[i] = base[(size_t)i * job.elem_stride];
-  __syncthreads();
   const float sgn = inverse ? 1.0f : -1.0f;
+  for (int i = threadIdx.x; i < len; i += 256) {
+    x[i] = base[(size_t)i * job.elem_stride];
+    double s, c;
+    sincospi((double)sgn * 2.0 * (double)i / (double)len, &s, &c);
+    w[i] = make_float2((float)c, (float)s);
+  }
+  __syncthreads();
   int ns = 1;
   int rem = len;
   while (rem > 1) {
     int r = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
     const int m = len / r;
+    const int wstep = len / (ns * r);  // W_{ns r}^{k q} = W_len^{k q wstep}
     for (int j = threadIdx.x; j < m; j += 256) {
       const int k = j % ns;
       float2 v[5];
       for (int q = 0; q < r; ++q) {
         float2 e = x[j + q * m];
-        if (q > 0 && k > 0) {  // twiddle in FP64, rounded once
-          double s, c;
-          sincospi((double)sgn * 2.0 * (double)(k * q) / (double)(ns * r), &s, &c);
-          e = cmul(e, make_float2((float)c, (float)s));
-        }
+        if (q > 0 && k > 0) e = cmul(e, w[k * q * wstep]);
         v[q] = e;
       }
       if (r == 2) {
@@ -2464,7 +2467,7 @@ hipError_t launch_init_state(const TileDev* tiles, const int* ids, int count, in
 hipError_t launch_line_fft(const LineJob* jobs, int njobs, int len, int max_lines, int inverse,
                            hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  const size_t lds = (size_t)2 * len * sizeof(float2);
+  const size_t lds = (size_t)3 * len * sizeof(float2);
   hipLaunchKernelGGL(line_fft_kernel, dim3(max_lines, njobs), dim3(256), lds, st, jobs, len,
                      inverse);
   return hipGetLastError();
