@@ -103,7 +103,9 @@ hipError_t launch_update(int n, const TileDev* tiles, const Item* items, int cou
 hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, int count,
                                float* out, const int64_t* out_off, int nd_max,
                                float2* big_scratch, hipStream_t st);
-hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
+// rows: workgroups per tile, at least every listed tile's support-row count
+// (the tile side n always is)
+hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int rows,
                                hipStream_t st);
 hipError_t launch_iter_end(const TileDev* tiles, const int* tile_ids, int count, int iter,
                            hipStream_t st);

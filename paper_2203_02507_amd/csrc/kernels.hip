@@ -1876,7 +1876,14 @@ __global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __rest
   for (int kx = ch.x + (int)threadIdx.x; kx <= ch.y; kx += 128) {
     const int px = ky * n + kx;
     float2 acc = t.dP[px];
-    for (int m = 1; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * nn + px]);
+    int m = 1;
+    // four increments requested at a time, summed in slot order
+    for (; m + 4 <= s.count; m += 4) {
+      const float2 d0 = t.dP[(size_t)m * nn + px], d1 = t.dP[(size_t)(m + 1) * nn + px];
+      const float2 d2 = t.dP[(size_t)(m + 2) * nn + px], d3 = t.dP[(size_t)(m + 3) * nn + px];
+      acc = cadd(cadd(cadd(cadd(acc, d0), d1), d2), d3);
+    }
+    for (; m < s.count; ++m) acc = cadd(acc, t.dP[(size_t)m * nn + px]);
     t.P[px] = pupil_mean_step(t.P[px], acc, s.count);
   }
 }
@@ -2434,10 +2441,10 @@ hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, i
   }
 }
 
-hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int n,
+hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int rows,
                                hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pupil_reduce_kernel, dim3(n, count), dim3(128), 0, st, tiles, steps);
+  hipLaunchKernelGGL(pupil_reduce_kernel, dim3(rows, count), dim3(128), 0, st, tiles, steps);
   return hipGetLastError();
 }
 

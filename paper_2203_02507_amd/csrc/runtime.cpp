@@ -394,15 +394,17 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
         Launch r{};
         r.kind = Launch::REDUCE;
         r.off = (int)steptiles.size();
-        int nmax = 0;
+        int nmax = 0, ndmax = 0;
         for (int t : active) {
           const TilePlan& tp = tiles[t];
           if (host_tiles[t].mode != 2 || s >= tp.nsteps || seq_done[t]) continue;
           steptiles.push_back(StepTile{t, tp.step_beg[s + 1] - tp.step_beg[s]});
           nmax = std::max(nmax, tp.n);
+          ndmax = std::max(ndmax, tp.nd);
         }
         r.count = (int)steptiles.size() - r.off;
         r.n = nmax;
+        r.nd_max = ndmax;
         if (r.count > 0) launches.push_back(r);
       }
       if (!active.empty()) {
@@ -774,7 +776,7 @@ hipError_t Executor::enqueue_range(size_t begin, size_t end, hipStream_t s) {
         e = launch_update_class(l, tab, it + l.off, s, (const int2*)ranges_d.p);
         break;
       case Launch::REDUCE:
-        e = launch_pupil_reduce(tab, stp + l.off, l.count, l.n, s);
+        e = launch_pupil_reduce(tab, stp + l.off, l.count, l.nd_max > 0 ? l.nd_max : l.n, s);
         break;
       case Launch::ITER_END:
         e = launch_iter_end(tab, ids + l.off, l.count, l.iter, s);

@@ -36,7 +36,7 @@ struct DevBuf {
 
 struct Launch {
   enum Kind { INIT, UPDATE, REDUCE, ITER_END, SMAX } kind = INIT;
-  int n = 0, nd_max = 0;   // UPDATE: tile side, largest support-column count
+  int n = 0, nd_max = 0;   // UPDATE, REDUCE: tile side, largest support-column count
   int prec = 0;            // UPDATE: fpm_precision of every item of the launch
   int box_max = 0;         // UPDATE, MFMA: largest support box
   const uint16_t* tabE = nullptr;  // UPDATE, MFMA: DFT tables
