@@ -1865,7 +1865,7 @@ __global__ __launch_bounds__(kBigThreads) void forward_kernel_big(const TileDev*
 // Block (r, tile): support row ky = kx0 + r (D0 is symmetric under
 // transposition, so the column chords are also the row chords); threads run
 // along the row, so every access is contiguous.
-__global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
+__global__ __launch_bounds__(64) void pupil_reduce_kernel(const TileDev* __restrict__ tiles,
                                                            const StepTile* __restrict__ steps) {
   const StepTile s = steps[blockIdx.y];
   const TileDev t = tiles[s.tile];
@@ -1873,7 +1873,7 @@ __global__ __launch_bounds__(128) void pupil_reduce_kernel(const TileDev* __rest
   const int n = t.n, nn = n * n;
   const int ky = t.kx0 + blockIdx.x;
   const int2 ch = t.chord[ky];
-  for (int kx = ch.x + (int)threadIdx.x; kx <= ch.y; kx += 128) {
+  for (int kx = ch.x + (int)threadIdx.x; kx <= ch.y; kx += 64) {
     const int px = ky * n + kx;
     float2 acc = t.dP[px];
     int m = 1;
@@ -2444,7 +2444,7 @@ hipError_t launch_forward_leds(int n, const TileDev* tiles, const Item* items, i
 hipError_t launch_pupil_reduce(const TileDev* tiles, const StepTile* steps, int count, int rows,
                                hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pupil_reduce_kernel, dim3(rows, count), dim3(128), 0, st, tiles, steps);
+  hipLaunchKernelGGL(pupil_reduce_kernel, dim3(rows, count), dim3(64), 0, st, tiles, steps);
   return hipGetLastError();
 }
 
