@@ -80,8 +80,8 @@ def roofline(plan, prof):
     """Algorithmic HBM bytes of the update kernel per unit of its run time.
 
     Per LED-tile update: read the intensity image (4 n^2 B), read and write
-    the support pixels of the spectrum window (2 * 8 |D0| B).  The two chains
-    of tiles overlap their launches, so a launch's duration is not its cost:
+    the support pixels of the spectrum window (2 * 8 |D0| B).  The chains of
+    tiles overlap their launches, so a launch's duration is not its cost:
     achieved = algorithmic bytes of all update launches / the time at least
     one of them ran (the union of their intervals, HIP events); with one
     chain this is bytes per launch / mean launch duration."""
@@ -842,7 +842,8 @@ def main():
             "iterations": args.iterations, "updates_per_step": updates,
             "schedule": "led_groups", "precision": "fp32_fft",
             "graph": not args.no_graph,
-            "chains": int(os.environ.get("FPM_CHAINS", "2")),
+            # the library's default for a plan of one FP32 class up to 128 px
+            "chains": int(os.environ.get("FPM_CHAINS", str(min(4, plan.ntiles)))),
         },
         "roofline": roof,
         "cpu_baseline": cpu,

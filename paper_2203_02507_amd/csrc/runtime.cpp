@@ -204,8 +204,14 @@ fpm_status Executor::setup(const std::vector<TilePlan>& tiles) {
     u.first = std::max(u.first, tp.nd);
     u.second = std::max(u.second, mfma_box(tp.kx0, tp.nd));
   }
-  // number of chains of tiles (see below)
+  // number of chains of tiles (see below): four for a plan of one FP32 class
+  // of tiles up to 128 px (more of each chain's group-mean and iteration-end
+  // launches then overlap other chains' updates), otherwise two (a mixed
+  // plan puts its size classes on chains of their own first)
   int P = T >= 2 ? 2 : 1;
+  if (uclass.size() == 1 && uclass.begin()->first.first <= 128 &&
+      uclass.begin()->first.second == FPM_PREC_FP32_FFT)
+    P = std::min(4, T);
   if (const char* v = std::getenv("FPM_CHAINS")) {
     const int k = std::atoi(v);
     if (k >= 1 && k <= kMaxChains) P = std::min(k, T);
