@@ -2035,35 +2035,46 @@ __device__ __forceinline__ void dft5(float2 (&v)[5], bool inv) {
 }
 }  // namespace
 
+// C lines of one job per workgroup (256 / C threads per line): the lines'
+// elements are loaded and stored with the line index fastest where lines are
+// closer in memory than elements (column passes: runs of C adjacent values
+// per row instead of one value per row), element index fastest otherwise.
 __global__ __launch_bounds__(256) void line_fft_kernel(const LineJob* __restrict__ jobs, int len,
-                                                       int inverse) {
+                                                       int inverse, int C) {
   const LineJob job = jobs[blockIdx.y];
-  const int line = blockIdx.x;
-  if (line >= job.nlines) return;
+  const int line0 = blockIdx.x * C;
+  if (line0 >= job.nlines) return;  // the whole workgroup
   extern __shared__ float2 lbuf[];
   float2* x = lbuf;
-  float2* y = lbuf + len;
-  float2* w = lbuf + 2 * len;  // w[e] = W_len^e, in FP64 and rounded once
-  float2* base = job.base + (size_t)line * job.line_stride;
+  float2* y = lbuf + C * len;
+  float2* w = lbuf + 2 * C * len;  // w[e] = W_len^e, in FP64 and rounded once
   const float sgn = inverse ? 1.0f : -1.0f;
+  const bool line_fast = job.line_stride < job.elem_stride;
   for (int i = threadIdx.x; i < len; i += 256) {
-    x[i] = base[(size_t)i * job.elem_stride];
     double s, c;
     sincospi((double)sgn * 2.0 * (double)i / (double)len, &s, &c);
     w[i] = make_float2((float)c, (float)s);
   }
+  for (int idx = threadIdx.x; idx < C * len; idx += 256) {
+    const int c = line_fast ? idx % C : idx / len, i = line_fast ? idx / C : idx % len;
+    if (line0 + c < job.nlines)
+      x[c * len + i] = job.base[(size_t)(line0 + c) * job.line_stride + (size_t)i * job.elem_stride];
+  }
   __syncthreads();
+  const int tpl = 256 / C, lc = threadIdx.x / tpl, lt = threadIdx.x % tpl;
   int ns = 1;
   int rem = len;
   while (rem > 1) {
     int r = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
     const int m = len / r;
     const int wstep = len / (ns * r);  // W_{ns r}^{k q} = W_len^{k q wstep}
-    for (int j = threadIdx.x; j < m; j += 256) {
+    const float2* xl = x + lc * len;
+    float2* yl = y + lc * len;
+    for (int j = lt; j < m; j += tpl) {
       const int k = j % ns;
       float2 v[5];
       for (int q = 0; q < r; ++q) {
-        float2 e = x[j + q * m];
+        float2 e = xl[j + q * m];
         if (q > 0 && k > 0) e = cmul(e, w[k * q * wstep]);
         v[q] = e;
       }
@@ -2085,7 +2096,7 @@ __global__ __launch_bounds__(256) void line_fft_kernel(const LineJob* __restrict
         dft5(v, inverse);
       }
       const int d = (j / ns) * ns * r + k;
-      for (int q = 0; q < r; ++q) y[d + q * ns] = v[q];
+      for (int q = 0; q < r; ++q) yl[d + q * ns] = v[q];
     }
     __syncthreads();
     float2* tmp = x;
@@ -2094,10 +2105,14 @@ __global__ __launch_bounds__(256) void line_fft_kernel(const LineJob* __restrict
     ns *= r;
     rem /= r;
   }
-  for (int i = threadIdx.x; i < len; i += 256) {
-    float2 v = cscale(x[i], job.scale);
-    if (job.modulate && ((line + i) & 1)) v = make_float2(-v.x, -v.y);
-    base[(size_t)i * job.elem_stride] = v;
+  for (int idx = threadIdx.x; idx < C * len; idx += 256) {
+    const int c = line_fast ? idx % C : idx / len, i = line_fast ? idx / C : idx % len;
+    const int line = line0 + c;
+    if (line < job.nlines) {
+      float2 v = cscale(x[c * len + i], job.scale);
+      if (job.modulate && ((line + i) & 1)) v = make_float2(-v.x, -v.y);
+      job.base[(size_t)line * job.line_stride + (size_t)i * job.elem_stride] = v;
+    }
   }
 }
 
@@ -2474,9 +2489,12 @@ hipError_t launch_init_state(const TileDev* tiles, const int* ids, int count, in
 hipError_t launch_line_fft(const LineJob* jobs, int njobs, int len, int max_lines, int inverse,
                            hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  const size_t lds = (size_t)3 * len * sizeof(float2);
-  hipLaunchKernelGGL(line_fft_kernel, dim3(max_lines, njobs), dim3(256), lds, st, jobs, len,
-                     inverse);
+  // lines per workgroup: the largest power of two (at most 8) with C len <= 2048
+  int C = 1;
+  while (C < 8 && 2 * C * len <= 2048) C *= 2;
+  const size_t lds = (size_t)(2 * C + 1) * len * sizeof(float2);
+  hipLaunchKernelGGL(line_fft_kernel, dim3((max_lines + C - 1) / C, njobs), dim3(256), lds, st,
+                     jobs, len, inverse, C);
   return hipGetLastError();
 }
 
